@@ -1,0 +1,225 @@
+/*
+ * moc.h - C ABI of the MI355X fixed-source 3D method-of-characteristics
+ * transport library (gfx950, HIP).
+ *
+ * The library computes the per-iteration transport sweep of 3D MOC
+ * (paper section 2.1, Eqs. 1-4) over 3D characteristic tracks generated on the
+ * fly from stored 2D radial tracks and axial z-stacks (section 2.2, Eqs. 5-11;
+ * section 3.2, Eq. 13), inside fixed-source source iteration:
+ *
+ *   geometry + track parameters + multigroup cross sections + fixed source
+ *     -> converged FSR scalar flux.
+ *
+ * Conventions shared by every entry point
+ *  - Every function returns MOC_OK (0) or a negative moc_status and never
+ *    throws.  The text of the last error of the calling thread is returned by
+ *    moc_last_error(); it stays valid until that thread's next call.
+ *  - Host arrays passed in are read during the call only (copied); the caller
+ *    keeps ownership and may free them on return.
+ *  - Device memory is never allocated in the solve path: the caller passes a
+ *    device workspace of at least moc_plan_info.workspace_bytes bytes (any
+ *    device allocation, e.g. a torch uint8 tensor) and keeps it alive while
+ *    the solver exists.  The stream is caller-owned (a hipStream_t passed as
+ *    void*; NULL = the default stream).  All device work of a solver is issued
+ *    on that stream; calls that return host data synchronise it.
+ *  - Numbering contract:
+ *      cell     = cy*nx + cx
+ *      local    = 2*sector + (inside ? 0 : 1)   when inclusion_radius > 0
+ *               = sector                        otherwise
+ *      sector   = floor(atan2(y-yc, x-xc) mod 2pi / (2pi/n_sectors) + 1e-9)
+ *                 mod n_sectors  (points on a sector line join the sector
+ *                 that starts there)
+ *      region r = cell*regions_per_cell + local
+ *      FSR j    = r*n_layers + k,   k = floor(z / (height/n_layers))
+ *    Fluxes and sources are [n_fsr][n_groups] row-major doubles.
+ *  - 3D segments shorter than 1e-9 cm are dropped; a z-stack line is a 3D
+ *    track only if it runs more than 1e-9 cm (2D length) inside the box, and a
+ *    track leaving within 1e-9 cm of a box edge reflects across both faces.
+ *  - Directed 3D tracks: stored tracks are numbered in z-stack order
+ *    (Eq. 13: stored azimuth, 2D track within azimuth, polar angle, position
+ *    in the stack); each is swept forward (dir 0) and backward (dir 1).
+ */
+#ifndef MOC_H
+#define MOC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MOC_API __attribute__((visibility("default")))
+
+typedef enum {
+    MOC_OK = 0,
+    MOC_EINVAL = -1,    /* invalid argument: bad geometry, tracking, XS, source, size */
+    MOC_ENOMEM = -2,    /* workspace / budget smaller than required                  */
+    MOC_EDEVICE = -3,   /* a HIP runtime error; moc_last_error() carries its text    */
+    MOC_ENOTCONV = -4,  /* max_iters reached before tol; the flux is still valid     */
+    MOC_EBUSY = -5      /* serving: request not finished yet                         */
+} moc_status;
+
+enum { MOC_BC_VACUUM = 0, MOC_BC_REFLECTIVE = 1 };
+enum { MOC_FACE_XMIN = 0, MOC_FACE_XMAX, MOC_FACE_YMIN, MOC_FACE_YMAX, MOC_FACE_ZMIN, MOC_FACE_ZMAX };
+
+/* Axially extruded pin-cell lattice (paper section 2.2: radial geometry
+ * identical on every axial plane, materials per radial region).
+ * Box [0, nx*pitch] x [0, ny*pitch] x [0, height], n_layers equal layers. */
+typedef struct {
+    int nx, ny;
+    double pitch;
+    double inclusion_radius;   /* 0: plain square cell; else < pitch/2            */
+    int n_sectors;             /* 1, 2, 4, 8 or 16 equal sectors starting at +x   */
+    double height;
+    int n_layers;
+    int bc[6];                 /* per face, MOC_BC_* (x-, x+, y-, y+, z-, z+)     */
+    const int *cell_material;  /* [ny*nx][2] = {inside, outside} material ids     */
+} moc_geometry;
+
+/* Track laydown: n_azim azimuthal angles over [0, 2pi) (multiple of 4),
+ * n_polar Gauss-Legendre polar angles over (0, pi) (even), radial track
+ * spacing and axial ray spacing (Eq. 5's delta z) in cm.  Both are adjusted
+ * down to the nearest cyclic values. */
+typedef struct {
+    int n_azim, n_polar;
+    double radial_spacing, axial_spacing;
+} moc_tracking;
+
+/* Multigroup cross sections, isotropic scattering.
+ * sigma_t [M][G] > 0, sigma_s [M][G][G] >= 0 indexed [m][g_from][g_to],
+ * with sum_{g_to} sigma_s[m][g][g_to] < sigma_t[m][g] (source iteration
+ * then contracts).  1 <= G <= 64. */
+typedef struct {
+    int n_groups, n_materials;
+    const double *sigma_t;
+    const double *sigma_s;
+} moc_xs;
+
+typedef struct moc_plan moc_plan;
+typedef struct moc_solver moc_solver;
+
+typedef struct {
+    long long n_fsr, n_regions;
+    long long n_2d_tracks, n_2d_segments;
+    long long n_stacks;        /* n_2d_tracks * n_polar                           */
+    long long n_3d_tracks;     /* stored 3D tracks (each swept in 2 directions)   */
+    long long n_chunks;        /* bundles of tracks_per_wave consecutive stack lines */
+    int n_groups, tracks_per_wave;
+    double dz;                 /* effective axial ray spacing                      */
+    size_t workspace_bytes;    /* device bytes moc_solver_create needs             */
+    size_t psi_bytes;          /* of which: the two boundary angular-flux buffers  */
+    size_t workspace_bytes_fp64; /* bytes for FP64 boundary flux (needed by the    */
+                                 /* FP64 sweep to keep full precision)             */
+} moc_plan_info;
+
+/* Solve controls.  sweep_fp64 = 1 runs segment arithmetic and angular flux in
+ * FP64 (precision study); exp_mode 0 = stable 1-e^-tau via expm1, 1 = the
+ * naive 1 - exp(-tau) with the hardware exponential (precision study only). */
+typedef struct {
+    double tol;                /* stop when the L-inf relative flux change < tol  */
+    int max_iters;
+    int sweep_fp64;
+    int exp_mode;
+} moc_solve_opts;
+
+typedef struct {
+    int iters;
+    double residual;           /* max_{j,g} |phi_k - phi_{k-1}| / phi_k            */
+    double balance_lhs;        /* sum_{j,g} sum_s W dpsi of the last sweep (FP64)  */
+    double balance_rhs;        /* sum W psi_in(k-1) - sum W psi_out(k), last sweep */
+    double absorption, leakage, source;  /* physical totals at the last iterate   */
+    unsigned long long seg_group_updates; /* per sweep: directed 3D segments x G  */
+    unsigned long long link_errors;       /* exits whose successor was not found  */
+    double sweep_ms_median;    /* median sweep-kernel time over the iterations    */
+} moc_stats;
+
+/* ---------------------------------------------------------------- plan */
+
+/* Host-side planning (paper section 3.1: geometry and 2D ray tracing on the
+ * CPU): quadrature, cyclic 2D laydown, 2D ray tracing of the radial geometry,
+ * reflective cycles and chain phases, z-stack table (Eq. 13) and the device
+ * footprint.  Returns MOC_EINVAL for: n_azim not a positive multiple of 4;
+ * n_polar odd or < 2; spacing <= 0; radius < 0 or >= pitch/2; n_sectors not
+ * in {1,2,4,8,16}; G outside [1,64]; sigma_t <= 0; sigma_s < 0; out-scatter
+ * ratio >= 1; material id out of range; bc not 0/1. */
+MOC_API int moc_plan_create(const moc_geometry *geom, const moc_tracking *trk, const moc_xs *xs,
+                            moc_plan **out);
+MOC_API int moc_plan_query(const moc_plan *plan, moc_plan_info *out);
+MOC_API void moc_plan_destroy(moc_plan *plan);   /* NULL-safe */
+
+/* Planner introspection (host, no device needed).  Sizes follow
+ * moc_plan_info; any pointer may be NULL to skip that output.
+ *  quadrature: phi [n_azim/2] corrected azimuths, dphi [n_azim/2] azimuthal
+ *    weights, spacing [n_azim/2] corrected radial spacing, cot [n_azim/2][n_polar]
+ *    corrected polar cotangents, weight [n_azim/2][n_polar] track weights
+ *    (solid angle x perpendicular area).
+ *  tracks2d: xy [n][4] start/end points, length [n], azim [n],
+ *    link [n][2] directed successor ids (2*t+d) of (t,fwd) and (t,bwd),
+ *    chain [n] chain coordinate of the start point, sigma [n] +1/-1.
+ *  stacks: zeta [n_stacks] phase of Eq. 5 in [0,dz), i_lo [n_stacks] index of
+ *    the lowest line, count [n_stacks] lines in the stack (3D tracks).
+ *  segments2d: pos [n_2d_segments] start position along its 2D track,
+ *    region [n_2d_segments], first [n_2d_tracks+1] offsets per 2D track. */
+MOC_API int moc_plan_quadrature(const moc_plan *plan, double *phi, double *dphi, double *spacing,
+                                double *cot, double *weight);
+MOC_API int moc_plan_tracks2d(const moc_plan *plan, double *xy, double *length, int *azim,
+                              long long *link, double *chain, int *sigma);
+MOC_API int moc_plan_stacks(const moc_plan *plan, double *zeta, long long *i_lo, long long *count);
+MOC_API int moc_plan_segments2d(const moc_plan *plan, double *pos, int *region, long long *first);
+/* Chunks: work item w = 2*chunk + dir covers stored tracks
+ * [first_track, first_track + n_tracks) swept in direction dir. */
+MOC_API int moc_plan_chunk(const moc_plan *plan, long long chunk, long long *first_track,
+                           int *n_tracks);
+
+/* ---------------------------------------------------------------- solver */
+
+/* Bind a plan to a caller-owned device workspace and stream; uploads the plan
+ * (2D segments, z-stack table, links, cross sections) and computes the
+ * track-estimated FSR volumes with one volume sweep.  ENOMEM when ws_bytes <
+ * workspace_bytes.  With ws_bytes >= workspace_bytes_fp64 the boundary
+ * angular flux is stored in FP64 (else FP32).  The plan may be destroyed
+ * afterwards. */
+MOC_API int moc_solver_create(const moc_plan *plan, void *dev_workspace, size_t ws_bytes,
+                              void *stream, moc_solver **out);
+MOC_API void moc_solver_destroy(moc_solver *s);   /* NULL-safe; does not free the workspace */
+
+/* Fixed volumetric isotropic source q [n_fsr][G] (>= 0), copied to the device. */
+MOC_API int moc_set_source(moc_solver *s, const double *q, size_t n);
+
+/* Source iteration from phi = 0, psi = 0 until residual < tol or max_iters.
+ * Returns MOC_OK, or MOC_ENOTCONV when max_iters was reached (flux valid). */
+MOC_API int moc_solve(moc_solver *s, const moc_solve_opts *opts, moc_stats *stats);
+
+/* Restart state (phi = 0, boundary psi = 0, iteration counter 0). */
+MOC_API int moc_reset(moc_solver *s);
+/* Run n further source iterations (source update, sweep, finalize) without a
+ * host synchronisation between them; stats (optional) synchronises once. */
+MOC_API int moc_iterate(moc_solver *s, int n, const moc_solve_opts *opts, moc_stats *stats);
+
+MOC_API int moc_get_flux(const moc_solver *s, double *host_out, size_t n);
+MOC_API int moc_get_volumes(const moc_solver *s, double *host_out, size_t n);
+MOC_API int moc_flux_device_ptr(const moc_solver *s, const double **dev);
+
+/* Test hook: one sweep of the listed work items (2*chunk + dir) only, from a
+ * given reduced source qhat [n_fsr][G] (rounded to the sweep precision) and
+ * incoming angular flux psi_in [n_items][tracks_per_wave][G] (lines beyond a
+ * chunk's count are ignored).  Returns the FSR tallies acc [n_fsr][G]
+ * (sum of W * delta_psi of those tracks) and every track's outgoing flux
+ * psi_out [n_items][tracks_per_wave][G]. */
+MOC_API int moc_sweep_items(moc_solver *s, long long n_items, const long long *items,
+                            const double *qhat, const double *psi_in, int sweep_fp64,
+                            double *acc_out, double *psi_out);
+
+/* Test hook: the 3D segments the GPU generates on the fly for stored tracks
+ * track_ids [n] (forward order): FSR ids and lengths written at
+ * [i*cap, i*cap + count[i]) of fsr_out / len_out (count may exceed cap, then
+ * only cap are written). */
+MOC_API int moc_trace_tracks(moc_solver *s, long long n, const long long *track_ids, int cap,
+                             int *fsr_out, double *len_out, int *count_out);
+
+MOC_API const char *moc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MOC_H */

@@ -26,7 +26,10 @@
 
 #define ORC_PI 3.14159265358979323846
 #define MATCH_TOL 1e-9
-#define MIN_SEG 1e-12
+/* segments shorter than this (cm) are dropped: structural zero-length pieces
+ * (a plane crossing that coincides with a surface crossing) carry rounding
+ * noise of the chain phase, far below this */
+#define MIN_SEG 1e-9
 /* a z-stack line is a 3D track only if it runs more than this 2D length
  * inside the box; lines that merely graze a box edge are not tracks */
 #define TRACK_EPS 1e-9
@@ -213,8 +216,9 @@ static long long fsr_at(const struct orc_model *m, double x, double y, double z,
     if (m->ns > 1) {
         double ang = atan2(dy, dx);
         if (ang < 0) ang += 2.0 * ORC_PI;
-        s = (int)floor(ang / (2.0 * ORC_PI / m->ns));
-        if (s >= m->ns) s = m->ns - 1;
+        /* a point within 1e-9 of a sector line belongs to the sector that
+         * starts at that line (tracks that run along a sector line) */
+        s = ((int)floor(ang / (2.0 * ORC_PI / m->ns) + 1e-9)) % m->ns;
         if (s < 0) s = 0;
     }
     int local = (m->R > 0) ? 2 * s + (inside ? 0 : 1) : s;
@@ -290,14 +294,17 @@ static long long trace3d(const struct orc_model *m, const double *p0, const doub
                 }
             }
             if (m->ns > 1 && dxy2 > 0) {
-                for (int s = 0; s < m->ns; ++s) {
+                /* with an even sector count the half-lines at angle a and
+                 * a + pi are both sector boundaries: intersect the full lines
+                 * through the cell centre (a track through the centre then
+                 * splits there whatever the rounding) */
+                for (int s = 0; s < m->ns / 2; ++s) {
                     double al = 2.0 * ORC_PI * s / m->ns;
                     double ex = cos(al), ey = sin(al);
                     double dxe = d[0] * ey - d[1] * ex;     /* d x e */
                     if (dxe == 0.0) continue;
                     double t = (wx * ey - wy * ex) / dxe;   /* (w x e)/(d x e) */
-                    double u = (wx * d[1] - wy * d[0]) / dxe; /* (w x d)/(d x e) */
-                    if (u > 0 && t > ta && t < tb) PUSH(t);
+                    if (t > ta && t < tb) PUSH(t);
                 }
             }
         }
@@ -769,6 +776,12 @@ int orc_track_info(const orc_model *m, long long track, double *p01, long long *
         if (!m->traced) return -2;
         succ[0] = m->succ[2 * track]; succ[1] = m->succ[2 * track + 1];
     }
+    return 0;
+}
+
+int orc_segment_counts(const orc_model *m, long long *counts) {
+    if (!m->traced) return -2;
+    for (long long tr = 0; tr < m->n3d; ++tr) counts[tr] = m->seg_off[tr + 1] - m->seg_off[tr];
     return 0;
 }
 

@@ -83,6 +83,9 @@ long long orc_trace_track(const orc_model *m, long long track, int *fsr, double 
  * Only valid after a traced build. */
 int orc_track_info(const orc_model *m, long long track, double *p01, long long *succ);
 
+/* Number of segments of every stored 3D track [n_3d_tracks] (traced build). */
+int orc_segment_counts(const orc_model *m, long long *counts);
+
 /* Track-estimated FSR volumes [n_fsr] (valid after a traced build). */
 int orc_volumes(const orc_model *m, double *vol);
 

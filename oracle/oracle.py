@@ -71,6 +71,7 @@ def lib():
         L.orc_trace_track.restype = C.c_longlong
         L.orc_track_info.argtypes = [C.c_void_p, C.c_longlong, C.c_void_p, C.c_void_p]
         L.orc_volumes.argtypes = [C.c_void_p, C.c_void_p]
+        L.orc_segment_counts.argtypes = [C.c_void_p, C.c_void_p]
         L.orc_solve.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_int, C.c_void_p,
                                 C.c_void_p, P(_Result)]
         L.orc_sweep_sample.argtypes = [C.c_void_p, C.c_longlong, C.c_void_p, C.c_void_p,
@@ -181,6 +182,11 @@ class Model:
 
     def weight(self, track: int) -> float:
         return lib().orc_track_weight(self._h, int(track))
+
+    def segment_counts(self):
+        c = np.zeros(self.info["n_3d_tracks"], np.int64)
+        assert lib().orc_segment_counts(self._h, _ptr(c)) == 0
+        return c
 
     def volumes(self):
         v = np.zeros(self.info["n_fsr"])

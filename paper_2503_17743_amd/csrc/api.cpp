@@ -1,0 +1,289 @@
+// C ABI entry points (declared in include/moc.h): argument checking, plan and
+// solver lifetime, and the source-iteration driver.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "plan.hpp"
+#include "solver.hpp"
+
+using moc::set_error;
+
+namespace {
+
+int fail(int code, const std::string &msg) {
+    set_error(msg);
+    return code;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *moc_last_error(void) { return moc::last_error(); }
+
+int moc_plan_create(const moc_geometry *geom, const moc_tracking *trk, const moc_xs *xs,
+                    moc_plan **out) {
+    if (!out) return fail(MOC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!geom || !trk || !xs) return fail(MOC_EINVAL, "NULL argument");
+    moc_plan *p = new (std::nothrow) moc_plan();
+    if (!p) return fail(MOC_ENOMEM, "host allocation failed");
+    std::string err;
+    try {
+        err = p->p.build(*geom, *trk, *xs);
+    } catch (const std::bad_alloc &) {
+        delete p;
+        return fail(MOC_ENOMEM, "host allocation failed while planning");
+    }
+    if (!err.empty()) {
+        delete p;
+        return fail(MOC_EINVAL, err);
+    }
+    *out = p;
+    set_error("");
+    return MOC_OK;
+}
+
+int moc_plan_query(const moc_plan *plan, moc_plan_info *out) {
+    if (!plan || !out) return fail(MOC_EINVAL, "NULL argument");
+    *out = plan->p.info();
+    return MOC_OK;
+}
+
+void moc_plan_destroy(moc_plan *plan) { delete plan; }
+
+int moc_plan_quadrature(const moc_plan *plan, double *phi, double *dphi, double *spacing,
+                        double *cot, double *weight) {
+    if (!plan) return fail(MOC_EINVAL, "NULL plan");
+    const moc::Plan &p = plan->p;
+    for (int a = 0; a < p.A2; ++a) {
+        if (phi) phi[a] = p.phi[a];
+        if (dphi) dphi[a] = p.dphi[a];
+        if (spacing) spacing[a] = p.deff[a];
+    }
+    for (size_t i = 0; i < p.cot.size(); ++i) {
+        if (cot) cot[i] = p.cot[i];
+        if (weight) weight[i] = p.wgt[i];
+    }
+    return MOC_OK;
+}
+
+int moc_plan_tracks2d(const moc_plan *plan, double *xy, double *length, int *azim,
+                      long long *link, double *chain, int *sigma) {
+    if (!plan) return fail(MOC_EINVAL, "NULL plan");
+    const moc::Plan &p = plan->p;
+    for (int64_t t = 0; t < p.n2d; ++t) {
+        if (xy) {
+            xy[4 * t] = p.x0[t];
+            xy[4 * t + 1] = p.y0[t];
+            xy[4 * t + 2] = p.x1[t];
+            xy[4 * t + 3] = p.y1[t];
+        }
+        if (length) length[t] = p.L[t];
+        if (azim) azim[t] = p.az[t];
+        if (link) {
+            link[2 * t] = p.link[2 * t];
+            link[2 * t + 1] = p.link[2 * t + 1];
+        }
+        if (chain) chain[t] = p.chain[t];
+        if (sigma) sigma[t] = p.sig[t];
+    }
+    return MOC_OK;
+}
+
+int moc_plan_stacks(const moc_plan *plan, double *zeta, long long *i_lo, long long *count) {
+    if (!plan) return fail(MOC_EINVAL, "NULL plan");
+    const moc::Plan &p = plan->p;
+    for (int64_t s = 0; s < p.n_stacks; ++s) {
+        if (zeta) zeta[s] = p.zeta[s];
+        if (i_lo) i_lo[s] = p.ilo[s];
+        if (count) count[s] = p.cnt[s];
+    }
+    return MOC_OK;
+}
+
+int moc_plan_segments2d(const moc_plan *plan, double *pos, int *region, long long *first) {
+    if (!plan) return fail(MOC_EINVAL, "NULL plan");
+    const moc::Plan &p = plan->p;
+    for (size_t k = 0; k < p.seg_pos.size(); ++k) {
+        if (pos) pos[k] = p.seg_pos[k];
+        if (region) region[k] = p.seg_reg[k];
+    }
+    if (first)
+        for (int64_t t = 0; t <= p.n2d; ++t) first[t] = p.seg_first[t];
+    return MOC_OK;
+}
+
+int moc_plan_chunk(const moc_plan *plan, long long chunk, long long *first_track, int *n_tracks) {
+    if (!plan) return fail(MOC_EINVAL, "NULL plan");
+    const moc::Plan &p = plan->p;
+    if (chunk < 0 || chunk >= p.n_chunks) return fail(MOC_EINVAL, "chunk out of range");
+    int64_t lo = 0, hi = p.n_stacks;
+    while (hi - lo > 1) {
+        int64_t mid = (lo + hi) / 2;
+        if (p.chunk_off[mid] <= chunk) lo = mid;
+        else hi = mid;
+    }
+    int64_t z0 = (chunk - p.chunk_off[lo]) * p.T;
+    int64_t n = std::min<int64_t>(p.T, p.cnt[lo] - z0);
+    if (first_track) *first_track = p.trk_off[lo] + z0;
+    if (n_tracks) *n_tracks = (int)n;
+    return MOC_OK;
+}
+
+int moc_solver_create(const moc_plan *plan, void *dev_workspace, size_t ws_bytes, void *stream,
+                      moc_solver **out) {
+    if (!out) return fail(MOC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!plan || !dev_workspace) return fail(MOC_EINVAL, "NULL plan or workspace");
+    const moc::Plan &p = plan->p;
+    moc_solver *sv = new (std::nothrow) moc_solver();
+    if (!sv) return fail(MOC_ENOMEM, "host allocation failed");
+    moc::Solver &s = sv->s;
+    s.info = p.info();
+    s.lay = moc::make_layout(p, ws_bytes >= s.info.workspace_bytes_fp64);
+    if (ws_bytes < s.lay.total) {
+        delete sv;
+        return fail(MOC_ENOMEM, "workspace smaller than moc_plan_info.workspace_bytes");
+    }
+    if ((reinterpret_cast<uintptr_t>(dev_workspace) & 255) != 0) {
+        delete sv;
+        return fail(MOC_EINVAL, "workspace must be 256-byte aligned");
+    }
+    s.ws = static_cast<char *>(dev_workspace);
+    s.stream = static_cast<hipStream_t>(stream);
+    s.P = p.P;
+    s.K = p.K;
+    s.H = p.H;
+    s.h = p.h;
+    std::memcpy(s.bc, p.bc, sizeof(s.bc));
+    int rc = s.upload(p);
+    if (!rc) rc = moc::fill_zero(s.ws + s.lay.off_q, (size_t)p.n_fsr * p.G * 8, s.stream);
+    if (!rc) rc = s.compute_volumes();
+    if (!rc) rc = s.reset();
+    if (rc) {
+        delete sv;
+        return rc;
+    }
+    *out = sv;
+    return MOC_OK;
+}
+
+void moc_solver_destroy(moc_solver *s) { delete s; }
+
+int moc_set_source(moc_solver *sv, const double *q, size_t n) {
+    if (!sv || !q) return fail(MOC_EINVAL, "NULL argument");
+    moc::Solver &s = sv->s;
+    const size_t need = (size_t)s.info.n_fsr * s.info.n_groups;
+    if (n != need) return fail(MOC_EINVAL, "source size must be n_fsr * n_groups");
+    for (size_t i = 0; i < n; ++i)
+        if (!(q[i] >= 0) || !std::isfinite(q[i])) return fail(MOC_EINVAL, "source must be finite and >= 0");
+    hipError_t e = hipMemcpyAsync(s.ws + s.lay.off_q, q, n * 8, hipMemcpyHostToDevice, s.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s.stream);
+    if (e != hipSuccess) return fail(MOC_EDEVICE, hipGetErrorString(e));
+    s.has_source = true;
+    return MOC_OK;
+}
+
+static int check_opts(const moc_solve_opts *o) {
+    if (!o) return fail(MOC_EINVAL, "NULL options");
+    if (o->max_iters < 1) return fail(MOC_EINVAL, "max_iters must be >= 1");
+    if (!(o->tol >= 0)) return fail(MOC_EINVAL, "tol must be >= 0");
+    if (o->exp_mode != 0 && o->exp_mode != 1) return fail(MOC_EINVAL, "exp_mode must be 0 or 1");
+    return MOC_OK;
+}
+
+int moc_reset(moc_solver *sv) {
+    if (!sv) return fail(MOC_EINVAL, "NULL solver");
+    return sv->s.reset();
+}
+
+int moc_iterate(moc_solver *sv, int n, const moc_solve_opts *opts, moc_stats *stats) {
+    if (!sv) return fail(MOC_EINVAL, "NULL solver");
+    if (n < 1) return fail(MOC_EINVAL, "n must be >= 1");
+    moc_solve_opts o{0.0, 1, 0, 0};
+    if (opts) {
+        int rc = check_opts(opts);
+        if (rc) return rc;
+        o = *opts;
+    }
+    int rc = sv->s.iterate(n, o, stats != nullptr);
+    if (rc) return rc;
+    if (stats) return sv->s.read_stats(stats);
+    return MOC_OK;
+}
+
+int moc_solve(moc_solver *sv, const moc_solve_opts *opts, moc_stats *stats) {
+    if (!sv) return fail(MOC_EINVAL, "NULL solver");
+    int rc = check_opts(opts);
+    if (rc) return rc;
+    moc::Solver &s = sv->s;
+    rc = s.reset();
+    if (rc) return rc;
+    double res = 1.0;
+    for (int k = 0; k < opts->max_iters; ++k) {
+        rc = s.iterate(1, *opts, true);
+        if (rc) return rc;
+        rc = s.read_residual(&res);
+        if (rc) return rc;
+        if (res < opts->tol) break;
+    }
+    if (stats) {
+        rc = s.read_stats(stats);
+        if (rc) return rc;
+    }
+    return res < opts->tol ? MOC_OK : MOC_ENOTCONV;
+}
+
+int moc_get_flux(const moc_solver *sv, double *host_out, size_t n) {
+    if (!sv || !host_out) return fail(MOC_EINVAL, "NULL argument");
+    const moc::Solver &s = sv->s;
+    if (n != (size_t)s.info.n_fsr * s.info.n_groups) return fail(MOC_EINVAL, "size must be n_fsr * n_groups");
+    hipError_t e = hipMemcpyAsync(host_out, s.ws + s.lay.off_phi, n * 8, hipMemcpyDeviceToHost, s.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s.stream);
+    if (e != hipSuccess) return fail(MOC_EDEVICE, hipGetErrorString(e));
+    return MOC_OK;
+}
+
+int moc_get_volumes(const moc_solver *sv, double *host_out, size_t n) {
+    if (!sv || !host_out) return fail(MOC_EINVAL, "NULL argument");
+    const moc::Solver &s = sv->s;
+    if (n != (size_t)s.info.n_fsr) return fail(MOC_EINVAL, "size must be n_fsr");
+    hipError_t e = hipMemcpyAsync(host_out, s.ws + s.lay.off_vol, n * 8, hipMemcpyDeviceToHost, s.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s.stream);
+    if (e != hipSuccess) return fail(MOC_EDEVICE, hipGetErrorString(e));
+    return MOC_OK;
+}
+
+int moc_flux_device_ptr(const moc_solver *sv, const double **dev) {
+    if (!sv || !dev) return fail(MOC_EINVAL, "NULL argument");
+    *dev = reinterpret_cast<const double *>(sv->s.ws + sv->s.lay.off_phi);
+    return MOC_OK;
+}
+
+int moc_sweep_items(moc_solver *sv, long long n_items, const long long *items, const double *qhat,
+                    const double *psi_in, int sweep_fp64, double *acc_out, double *psi_out) {
+    if (!sv || !items || !qhat || !psi_in || !acc_out || !psi_out) return fail(MOC_EINVAL, "NULL argument");
+    moc::Solver &s = sv->s;
+    for (long long i = 0; i < n_items; ++i)
+        if (items[i] < 0 || items[i] >= 2 * s.info.n_chunks) return fail(MOC_EINVAL, "work item out of range");
+    return s.sweep_items(n_items, items, qhat, psi_in, sweep_fp64, acc_out, psi_out);
+}
+
+int moc_trace_tracks(moc_solver *sv, long long n, const long long *track_ids, int cap, int *fsr_out,
+                     double *len_out, int *count_out) {
+    if (!sv || !track_ids || !fsr_out || !len_out || !count_out) return fail(MOC_EINVAL, "NULL argument");
+    if (cap < 1 || cap > 65536) return fail(MOC_EINVAL, "cap must be in [1, 65536]");
+    moc::Solver &s = sv->s;
+    if ((size_t)cap * 12 + 16 + 1024 > s.lay.scratch_bytes) return fail(MOC_EINVAL, "cap too large for the scratch area");
+    for (long long i = 0; i < n; ++i)
+        if (track_ids[i] < 0 || track_ids[i] >= s.info.n_3d_tracks) return fail(MOC_EINVAL, "track id out of range");
+    return s.trace_tracks(n, track_ids, cap, fsr_out, len_out, count_out);
+}
+
+}  // extern "C"

@@ -1,0 +1,53 @@
+// Device-side solver state: a plan bound to a caller workspace and stream.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "plan.hpp"
+
+namespace moc {
+
+struct SweepArgs;
+struct FsrArgs;
+
+void set_error(const std::string &e);
+const char *last_error();
+int fill_zero(void *p, size_t bytes, hipStream_t st);
+
+struct Solver {
+    Layout lay;
+    moc_plan_info info{};
+    char *ws = nullptr;
+    hipStream_t stream = nullptr;
+    int P = 2, K = 1;
+    double H = 1, h = 1;
+    int bc[6] = {0, 0, 0, 0, 0, 0};
+    int iter = 0;
+    bool has_source = false;
+    std::vector<float> sweep_ms;
+    std::vector<hipEvent_t> events;
+
+    SweepArgs sweep_args(int fp64, int exp_mode) const;
+    FsrArgs fsr_args() const;
+    int upload(const Plan &p);
+    int compute_volumes();
+    void launch_sweep(const SweepArgs &a, bool fp64);
+    int reset();
+    int iterate(int nit, const moc_solve_opts &o, bool time_sweep);
+    int read_stats(moc_stats *st);
+    int read_residual(double *r);
+    int sweep_items(long long n_items, const long long *items, const double *qhat,
+                    const double *psi_in, int fp64, double *acc_out, double *psi_out);
+    int trace_tracks(long long n, const long long *ids, int cap, int *fsr, double *len,
+                     int *count);
+    ~Solver();
+};
+
+}  // namespace moc
+
+struct moc_solver {
+    moc::Solver s;
+};

@@ -121,7 +121,7 @@ def _fsr_of_points(p, x, y, z):
     dy = y - (cy + 0.5) * p.pitch
     inside = (dx * dx + dy * dy) < p.radius ** 2 if p.radius > 0 else np.zeros_like(x, bool)
     ang = np.mod(np.arctan2(dy, dx), 2 * np.pi)
-    s = np.minimum(np.floor(ang / (2 * np.pi / p.n_sectors)).astype(int), p.n_sectors - 1)
+    s = np.floor(ang / (2 * np.pi / p.n_sectors) + 1e-9).astype(int) % p.n_sectors
     local = 2 * s + np.where(inside, 0, 1) if p.radius > 0 else s
     r = (cy * p.nx + cx) * p.regions_per_cell + local
     return r * p.n_layers + k
