@@ -1,0 +1,154 @@
+"""Benchmark: segment-group integrations per second of fixed-source 3D MOC
+source iterations on one MI355X.
+
+A step is one source iteration over the whole problem: source update, the
+on-the-fly 3D sweep (segment generation, Eq. 3 attenuation, FSR tally,
+boundary flux exchange) and the finalize pass.  Inputs are resident in HBM
+before the timed region.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload lattice8]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_SEG_GROUP = 12.0      # 4 B reduced-source gather + 8 B FP64 tally update
+
+
+def workload_desc(prob):
+    return (f"{prob.name}: {prob.nx}x{prob.ny} pin cells (pitch {prob.pitch} cm, inclusion "
+            f"r={prob.radius} cm, {prob.n_sectors} sectors x 2 rings), {prob.height:g} cm in "
+            f"{prob.n_layers} layers, {prob.n_groups} groups, {prob.n_azim} azimuthal x "
+            f"{prob.n_polar} polar, {prob.radial_spacing}/{prob.axial_spacing} cm spacing")
+
+
+def load_traffic(kernel_name, workload):
+    """HBM bytes per launch measured by rocprofv3 PMC runs, if recorded."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_hash") != kernel_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def kernel_hash():
+    import hashlib
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2503_17743_amd", "csrc", "sweep.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(prob, iters, threads):
+    from oracle import oracle as O
+    t0 = time.perf_counter()
+    m = O.Model(prob, n_threads=threads)
+    t1 = time.perf_counter()
+    phi, res = m.solve(max_iters=iters, tol=0.0)
+    t2 = time.perf_counter()
+    seg_groups = 2 * m.info["n_segments"] * prob.n_groups * iters
+    return phi, {
+        "value": seg_groups / (t2 - t1),
+        "unit": "seg-group/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"{iters} FP64 source iterations of the full {prob.name} problem "
+                   f"(trace/setup {t1 - t0:.1f} s excluded, sweep+update {t2 - t1:.1f} s)"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="lattice8")
+    ap.add_argument("--oracle-iters", type=int, default=6)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the sweep is single-GPU in this build "
+              "(multi-GPU angular decomposition is design-only)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2503_17743_amd import moc, problems as P
+
+    prob = P.get(args.workload)
+    torch.cuda.set_device(0)
+    plan = moc.Plan(prob)
+    solver = moc.Solver(plan, fp64_boundary=False)
+    solver.set_source(prob.q)
+
+    # parity of the path being timed: GPU iterates vs the FP64 oracle
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        threads = min(16, len(os.sched_getaffinity(0)))
+        ophi, cpu = cpu_baseline(prob, args.oracle_iters, threads)
+        solver.reset()
+        solver.iterate(args.oracle_iters, stats=False)
+        gphi = solver.flux()
+        parity = float(np.max(np.abs(gphi - ophi) / np.maximum(np.abs(ophi), 1e-300)))
+
+    solver.reset()
+    solver.iterate(args.warmup, stats=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = solver.iterate(args.steps, stats=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    segg = st["seg_group_updates"]
+    value = segg * args.steps / elapsed
+    sweep_s = st["sweep_ms_median"] * 1e-3
+    achieved = BYTES_PER_SEG_GROUP * segg / sweep_s / 1e9
+    traffic = load_traffic("k_sweep", args.workload)
+    line = {
+        "metric": "segment-group integrations/s at 1e-5 vs FP64",
+        "value": value,
+        "unit": "seg-group/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": workload_desc(prob),
+            "seg_group_updates_per_step": segg,
+            "n_fsr": plan.info["n_fsr"],
+            "n_3d_tracks": plan.info["n_3d_tracks"],
+            "accumulation": "f64",
+            "max_rel_err_vs_fp64_oracle": parity,
+            "parity_iterations": args.oracle_iters if parity is not None else None,
+            "sweep_ms_median": st["sweep_ms_median"],
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -99,6 +99,7 @@ std::string Plan::build(const moc_geometry &g, const moc_tracking &t, const moc_
     for (int f = 0; f < 6; ++f)
         if (g.bc[f] != MOC_BC_VACUUM && g.bc[f] != MOC_BC_REFLECTIVE) return "bc must be 0 or 1";
     if (x.n_groups < 1 || x.n_groups > 64) return "n_groups must be in [1, 64]";
+    if (t.n_polar > 64) return "n_polar must be <= 64";
     if (x.n_materials < 1) return "n_materials must be >= 1";
     if (!g.cell_material || !x.sigma_t || !x.sigma_s) return "null input array";
     nx = g.nx;
@@ -537,11 +538,15 @@ Layout make_layout(const Plan &p, bool psi64) {
     l.off_psi0 = take(psi);
     l.off_psi1 = take(psi);
     l.psi_bytes = 2 * ((psi + 255) & ~size_t(255));
+    l.off_work = take((size_t)2 * p.n2d * 4);
     l.off_scal = take(128 * 1024);
     l.n_item_cap = 4096;
     l.off_items = take(l.n_item_cap * 8);
     l.off_psi_entry = take(l.n_item_cap * 64 * 8);
     l.off_psi_exitb = take(l.n_item_cap * 64 * 8);
+    l.off_units = take(l.n_item_cap * 4);
+    l.off_filt_n = take(l.n_item_cap * 4);
+    l.off_filt_i0 = take(l.n_item_cap * 8);
     l.scratch_bytes = off - l.off_items;
     l.total = off;
     return l;

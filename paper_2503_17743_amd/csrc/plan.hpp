@@ -74,7 +74,9 @@ struct Layout {
     // scratch for the test hooks: work list + entry/exit flux per (wave, lane);
     // the same region holds traced segments
     size_t off_items = 0, off_psi_entry = 0, off_psi_exitb = 0;
+    size_t off_units = 0, off_filt_n = 0, off_filt_i0 = 0;
     size_t n_item_cap = 0, scratch_bytes = 0;
+    size_t off_work = 0;            // windowed-sweep work list (2 * n2d codes)
     bool psi64 = false;             // boundary angular flux stored in FP64
 };
 

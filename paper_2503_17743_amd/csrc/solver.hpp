@@ -29,12 +29,17 @@ struct Solver {
     bool has_source = false;
     std::vector<float> sweep_ms;
     std::vector<hipEvent_t> events;
+    int sw32 = 0, sw64 = 0;          // windowed sweep: 2D segments per window (0: direct path)
+    std::vector<long long> chunk_off, trk_off;
+    std::vector<int> cnt;
 
     SweepArgs sweep_args(int fp64, int exp_mode) const;
     FsrArgs fsr_args() const;
     int upload(const Plan &p);
     int compute_volumes();
-    void launch_sweep(const SweepArgs &a, bool fp64);
+    void launch_sweep(SweepArgs a, bool fp64, const int *units = nullptr, int n_units = 0,
+                      const int *filt_n = nullptr, const long long *filt_i0 = nullptr);
+    int window_size(bool fp64) const { return fp64 ? sw64 : sw32; }
     int reset();
     int iterate(int nit, const moc_solve_opts &o, bool time_sweep);
     int read_stats(moc_stats *st);

@@ -30,6 +30,7 @@
 namespace moc {
 
 constexpr double kFourPi = 12.566370614359172953850573533118;
+constexpr size_t kWinLdsBudget = 64 * 1024;   // dynamic LDS per windowed-sweep workgroup
 constexpr int kSlots = 64;        // spread of the scalar accumulators
 constexpr int kSlotStride = 16;   // doubles between slots (separate cache lines)
 
@@ -76,6 +77,8 @@ __device__ inline long long wave_sum_ll(long long v) {
     return v;
 }
 
+// 2D-length interval [ls, le] of the line z = base + c l inside the box
+// (0 <= l <= Lt, 0 <= z <= H)
 __device__ inline void clip_line(double base, double c, double Lt, double H, double &ls,
                                  double &le) {
     double a, b;
@@ -100,8 +103,6 @@ __device__ inline int seg_search(const double *__restrict__ pos, int lo, int hi,
     return lo;
 }
 
-// ------------------------------------------------------------------ sweep
-
 struct SweepArgs {
     const double *cot, *secl, *seca, *wgt;       // [A2][P]
     const double *t_len;                          // [n2d]
@@ -115,10 +116,10 @@ struct SweepArgs {
     const void *sigt;                             // [M][G] float or double
     const void *qhat;                             // [n_fsr][G] float or double
     double *acc;                                  // [n_fsr][G]
-    const void *psi_in;                           // boundary buffer read this sweep
+    void *psi_in;                                 // boundary buffer read this sweep
     void *psi_out;                                // boundary buffer written (may be null)
-    const double *psi_entry;                      // per (wave, lane) incoming flux (test hook)
-    double *psi_exit;                             // per (wave, lane) outgoing flux (test hook)
+    const double *psi_entry;                      // per (item, lane) incoming flux (test hook)
+    double *psi_exit;                             // per (item, lane) outgoing flux (test hook)
     const long long *items;                       // explicit work list or null
     long long n_items;
     long long n_stacks;
@@ -130,9 +131,115 @@ struct SweepArgs {
     int mode;                                     // 0 sweep, 1 volume tally
 };
 
-// One wave = one work item (2*chunk + dir).  Lanes beyond T*G or beyond the
-// stack's line count are inactive but follow the uniform loops.  R is the
-// segment arithmetic type, B the storage type of the boundary flux.
+// z of line i of stack s at the start of its 2D track (Eq. 5)
+__device__ inline double line_base(const SweepArgs &a, long long s, long long i) {
+    return a.zeta[s] + (double)(a.ilo[s] + i) * a.dz;
+}
+
+// Split the part [max(s0,ls), min(s1,le)] of the 2D segment [s0,s1] at the
+// axial planes crossed by the line z = base + c l and call f(layer, length)
+// for each 3D segment in sweep order (up: moving towards +z).  A line that
+// stays in one layer over the segment has length ds / sin(theta) (Eq. 8); a
+// line crossing a whole layer has length h / |cos(theta)| (Eq. 11); partial
+// pieces at the ends use the same z-extent rule.
+template <typename F>
+__device__ __forceinline__ int for_pieces(double s0, double s1, double ls, double le, double base,
+                                          double c, double h, int K, double secl, double seca,
+                                          bool up, F &&f) {
+    const double sa = fmax(s0, ls), sb = fmin(s1, le);
+    if (!(sa < sb)) return 0;
+    const double za = base + c * sa, zb = base + c * sb;
+    const double zlo = fmin(za, zb), zhi = fmax(za, zb);
+    int kl = (int)floor(zlo / h), kh = (int)ceil(zhi / h) - 1;
+    kl = min(max(kl, 0), K - 1);
+    kh = min(max(kh, kl), K - 1);
+    const int np = kh - kl + 1;
+    int m = 0;
+    for (int p = 0; p < np; ++p) {
+        const int kz = up ? kl + p : kh - p;
+        double l3;
+        if (np == 1) {
+            l3 = (sb - sa) * secl;
+        } else {
+            const double zl = fmax(zlo, kz * h), zh = fmin(zhi, (kz + 1) * h);
+            l3 = (zh - zl) * seca;
+        }
+        if (!(l3 >= kMinSeg)) continue;
+        f(kz, l3);
+        ++m;
+    }
+    return m;
+}
+
+// Where a directed line meets the box boundary at its start (at_exit false)
+// or end (at_exit true) in sweep order: kind 0 = a z face (at 2D position lz),
+// 1 = the side face at the 2D track end, 2 = the edge where both meet.
+struct Bound {
+    int kind;
+    int face_z, face_s;
+    double lz, zf, lside;
+};
+
+__device__ inline Bound boundary_of(double base, double c, double Lt, double H, int dir,
+                                    bool at_exit, int meta) {
+    Bound b;
+    const bool up = (c > 0) != (dir == 1);
+    const bool top = at_exit ? up : !up;
+    b.zf = top ? H : 0.0;
+    b.face_z = top ? MOC_FACE_ZMAX : MOC_FACE_ZMIN;
+    b.lz = (b.zf - base) / c;
+    const bool far_end = (dir == 0) == at_exit;     // the l = Lt end of the 2D track
+    b.lside = far_end ? Lt : 0.0;
+    b.face_s = far_end ? ((meta >> 20) & 0xf) : ((meta >> 16) & 0xf);
+    if (far_end) b.kind = (b.lz < Lt - kTrackEps) ? 0 : (b.lz > Lt + kTrackEps) ? 1 : 2;
+    else b.kind = (b.lz > kTrackEps) ? 0 : (b.lz < -kTrackEps) ? 1 : 2;
+    return b;
+}
+
+__device__ inline bool is_vacuum(const SweepArgs &a, const Bound &b) {
+    return (b.kind != 1 && a.bc[b.face_z] == MOC_BC_VACUUM) ||
+           (b.kind != 0 && a.bc[b.face_s] == MOC_BC_VACUUM);
+}
+
+// Directed slot (2 * stored track + dir) of the track that continues a line
+// leaving through reflective boundary b: specular reflection on a z face keeps
+// the 2D track and mirrors the polar angle; on a side face the 2D successor is
+// taken from the cyclic links; through an edge both apply.  The line index on
+// the successor's z-stack follows from matching z at the shared point (Eq. 5).
+// Returns -1 if no such line exists.
+__device__ inline long long successor_slot(const SweepArgs &a, const Bound &b, long long t, int n,
+                                           int dir, double base, double c) {
+    long long t2;
+    int d2, n2;
+    double l2, z2;
+    const int P = a.P;
+    if (b.kind == 0) {
+        t2 = t;
+        d2 = dir;
+        n2 = P - 1 - n;
+        l2 = b.lz;
+        z2 = b.zf;
+    } else {
+        const int lk = a.t_link[2 * t + dir];
+        t2 = lk >> 1;
+        d2 = lk & 1;
+        const bool same = (d2 == dir);
+        n2 = ((b.kind == 1) == same) ? n : P - 1 - n;
+        l2 = d2 == 0 ? 0.0 : a.t_len[t2];
+        z2 = b.kind == 1 ? base + c * b.lside : b.zf;
+    }
+    const long long s2 = t2 * P + n2;
+    const double c2 = a.cot[(a.t_meta[t2] & 0xffff) * P + n2];
+    const long long i2 = llrint((z2 - a.zeta[s2] - c2 * l2) / a.dz) - a.ilo[s2];
+    if (i2 < 0 || i2 >= (long long)a.cnt[s2]) return -1;
+    return 2 * (a.trk_off[s2] + i2) + d2;
+}
+
+// ------------------------------------------------------------------ direct sweep
+// One wave = one work item (2*chunk + dir): a bundle of T consecutive lines of
+// one z-stack, lane = (line, group), every 3D segment tallied with one FP64
+// global atomic.  Used when an LDS window of one 2D segment x all layers x
+// all groups does not fit (very large K*G).
 template <typename R, typename B>
 __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
     const int lane = threadIdx.x & 63;
@@ -141,7 +248,6 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
     const long long item = a.items ? a.items[w] : w;
     const int dir = (int)(item & 1);
     const long long chunk = item >> 1;
-    // stack of this chunk: largest s with chunk_off[s] <= chunk
     long long lo = 0, hi = a.n_stacks;
     while (hi - lo > 1) {
         long long mid = (lo + hi) >> 1;
@@ -153,154 +259,327 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
     const long long t = s / P;
     const int n = (int)(s - t * P);
     const int meta = a.t_meta[t];
-    const int az = meta & 0xffff;
-    const int an = az * P + n;
-    const double c = a.cot[an];
-    const double secl = a.secl[an];     // 3D length per unit 2D length (1/sin)
-    const double seca = a.seca[an];     // 3D length per unit height (1/|cos|)
-    const double W = a.wgt[an];
+    const int an = (meta & 0xffff) * P + n;
+    const double c = a.cot[an], secl = a.secl[an], seca = a.seca[an], W = a.wgt[an];
     const double Lt = a.t_len[t];
     const int f0 = a.t_first[t], f1 = a.t_first[t + 1];
     const int tr = lane / G;
     const int g = lane - tr * G;
     const long long zi = (chunk - a.chunk_off[s]) * a.T + tr;
     const bool active = (tr < a.T) && (zi < (long long)a.cnt[s]);
-    const double base = a.zeta[s] + (double)(a.ilo[s] + zi) * a.dz;
+    const double base = line_base(a, s, zi);
     double ls = 1e300, le = -1e300;
     if (active) clip_line(base, c, Lt, a.H, ls, le);
     const double l_lo = wave_min(ls), l_hi = wave_max(le);
     const long long slot_in = 2 * (a.trk_off[s] + zi) + dir;
-
     const R *sigt = (const R *)a.sigt;
     const R *qhat = (const R *)a.qhat;
     R psi = 0;
-    if (active) {
+    double s_in = 0.0;
+    if (active && a.mode == 0) {
         if (a.psi_entry) psi = (R)a.psi_entry[w * 64 + lane];
-        else if (a.mode == 0) psi = (R)((const B *)a.psi_in)[slot_in * G + g];
+        else if (!is_vacuum(a, boundary_of(base, c, Lt, a.H, dir, false, meta)))
+            psi = (R)((const B *)a.psi_in)[slot_in * G + g];
+        s_in = W * (double)psi;
     }
-    const double psi_start = (double)psi;
     long long nseg = 0;
-
     const int k_first = seg_search(a.seg_pos, f0, f1, l_lo);
     const int k_last = seg_search(a.seg_pos, f0, f1, l_hi);
-    const bool up = (c > 0) != (dir == 1);   // vertical motion in sweep order
+    const bool up = (c > 0) != (dir == 1);
     const int nk = k_last - k_first + 1;
     for (int kk = 0; kk < nk; ++kk) {
         const int k = dir ? (k_last - kk) : (k_first + kk);
         const double s0 = a.seg_pos[k];
         const double s1 = (k + 1 < f1) ? a.seg_pos[k + 1] : Lt;
         const int reg = a.seg_reg[k];
-        const long long jb = (long long)reg * K;
         if (!active) continue;
-        const double sa = fmax(s0, ls), sb = fmin(s1, le);
-        if (!(sa < sb)) continue;
-        const R st = (g < G) ? sigt[a.reg_mat[reg] * G + g] : (R)0;
-        const double za = base + c * sa, zb = base + c * sb;
-        const double zlo = fmin(za, zb), zhi = fmax(za, zb);
-        int kl = (int)floor(zlo / a.h), kh = (int)ceil(zhi / a.h) - 1;
-        kl = min(max(kl, 0), K - 1);
-        kh = min(max(kh, kl), K - 1);
-        const int np = kh - kl + 1;
-        for (int p = 0; p < np; ++p) {
-            const int kz = up ? kl + p : kh - p;
-            double l3;
-            if (np == 1) {
-                l3 = (sb - sa) * secl;                         // Eq. 8 case
-            } else {
-                const double zl = fmax(zlo, kz * a.h), zh = fmin(zhi, (kz + 1) * a.h);
-                l3 = (zh - zl) * seca;                         // Eq. 11 / partial
-            }
-            if (!(l3 >= kMinSeg)) continue;
+        const long long jb = (long long)reg * K;
+        const R st = sigt[a.reg_mat[reg] * G + g];
+        nseg += for_pieces(s0, s1, ls, le, base, c, a.h, K, secl, seca, up, [&](int kz, double l3) {
             const long long j = jb + kz;
-            ++nseg;
             if (a.mode == 1) {
                 if (g == 0) unsafeAtomicAdd(&a.acc[j], W * l3 / kFourPi);
-                continue;
+                return;
             }
             const R q = qhat[j * G + g];
-            const R F = one_minus_exp<R>(st * (R)l3, a.exp_mode);
-            const R d = (psi - q) * F;                         // Eq. 3
+            const R d = (psi - q) * one_minus_exp<R>(st * (R)l3, a.exp_mode);   // Eq. 3
             psi -= d;
             unsafeAtomicAdd(&a.acc[j * G + g], W * (double)d);
-        }
+        });
     }
     if (a.mode == 1) {
         const long long tot = wave_sum_ll(active && g == 0 ? nseg : 0);
-        if (lane == 0) atomicAdd((unsigned long long *)&a.scal[slot_index(Q_NSEG, (int)(w % kSlots))],
-                                 (unsigned long long)tot);
+        if (lane == 0)
+            atomicAdd((unsigned long long *)&a.scal[slot_index(Q_NSEG, (int)(w % kSlots))],
+                      (unsigned long long)tot);
         return;
     }
-
-    // ---- boundary angular flux: hand psi to the directed track that starts
-    // where this one leaves the box (specular reflection), or leak it.
-    double leak = 0.0;
+    double leak = 0.0, s_out = 0.0;
     long long link_err = 0;
     if (active) {
+        s_out = W * (double)psi;
         if (a.psi_exit) a.psi_exit[w * 64 + lane] = (double)psi;
-        const double zf = up ? a.H : 0.0;
-        const int face_z = up ? MOC_FACE_ZMAX : MOC_FACE_ZMIN;
-        const double lf = (zf - base) / c;       // where the line meets that face
-        int kind;                                 // 0 z-face, 1 side, 2 edge
-        if (dir == 0) kind = (lf < Lt - kTrackEps) ? 0 : (lf > Lt + kTrackEps) ? 1 : 2;
-        else kind = (lf > kTrackEps) ? 0 : (lf < -kTrackEps) ? 1 : 2;
-        const int face_s = dir == 0 ? ((meta >> 20) & 0xf) : ((meta >> 16) & 0xf);
-        bool vac = false;
-        if (kind != 1) vac |= (a.bc[face_z] == MOC_BC_VACUUM);
-        if (kind != 0) vac |= (a.bc[face_s] == MOC_BC_VACUUM);
-        if (vac) {
+        const Bound b = boundary_of(base, c, Lt, a.H, dir, true, meta);
+        if (is_vacuum(a, b)) {
             leak = W * (double)psi;
         } else if (a.psi_out) {
-            long long t2;
-            int d2, n2;
-            double l2, z2;
-            if (kind == 0) {
-                t2 = t;
-                d2 = dir;
-                n2 = P - 1 - n;
-                l2 = lf;
-                z2 = zf;
-            } else {
-                const int lk = a.t_link[2 * t + dir];
-                t2 = lk >> 1;
-                d2 = lk & 1;
-                const bool same = (d2 == dir);
-                n2 = (kind == 1) == same ? n : P - 1 - n;
-                l2 = d2 == 0 ? 0.0 : a.t_len[t2];
-                z2 = kind == 1 ? base + c * (dir == 0 ? Lt : 0.0) : zf;
-            }
-            const long long s2 = t2 * P + n2;
-            const int an2 = (a.t_meta[t2] & 0xffff) * P + n2;
-            const double c2 = a.cot[an2];
-            const long long i2 =
-                llrint((z2 - a.zeta[s2] - c2 * l2) / a.dz) - a.ilo[s2];
-            if (i2 >= 0 && i2 < (long long)a.cnt[s2]) {
-                const long long slot2 = 2 * (a.trk_off[s2] + i2) + d2;
-                ((B *)a.psi_out)[slot2 * G + g] = (B)psi;
-            } else {
+            const long long slot2 = successor_slot(a, b, t, n, dir, base, c);
+            if (slot2 >= 0) ((B *)a.psi_out)[slot2 * G + g] = (B)psi;
+            else {
                 link_err = 1;
                 leak = W * (double)psi;
             }
         }
     }
-    const double sin_ = wave_sum(active ? W * psi_start : 0.0);
-    const double sout = wave_sum(active ? W * (double)psi : 0.0);
-    const double lk = wave_sum(leak);
+    const double v_in = wave_sum(s_in), v_out = wave_sum(s_out), v_lk = wave_sum(leak);
     const long long ns = wave_sum_ll(active ? nseg : 0);
     const long long le_ = wave_sum_ll(link_err);
     if (lane == 0) {
         const int sl = (int)(w % kSlots);
-        unsafeAtomicAdd(&a.scal[slot_index(Q_SIN, sl)], sin_);
-        unsafeAtomicAdd(&a.scal[slot_index(Q_SOUT, sl)], sout);
-        unsafeAtomicAdd(&a.scal[slot_index(Q_LEAK, sl)], lk);
+        unsafeAtomicAdd(&a.scal[slot_index(Q_SIN, sl)], v_in);
+        unsafeAtomicAdd(&a.scal[slot_index(Q_SOUT, sl)], v_out);
+        unsafeAtomicAdd(&a.scal[slot_index(Q_LEAK, sl)], v_lk);
         atomicAdd((unsigned long long *)&a.scal[slot_index(Q_NSEG, sl)], (unsigned long long)ns);
         if (le_) atomicAdd((unsigned long long *)&a.scal[slot_index(Q_LINKERR, sl)], (unsigned long long)le_);
     }
 }
 
+// ------------------------------------------------------------------ windowed sweep
+// One workgroup = one 2D track in one sweep direction (every polar stack,
+// every line).  The track's 2D segments are walked in windows of Sw segments.
+// For each window the reduced source of all Sw x K x G FSR-groups the window
+// can touch is staged in LDS (for a segment they are contiguous: FSRs
+// r*K .. r*K+K-1, layer-fastest) and an FP64 LDS tally of the same shape
+// collects W * delta_psi from every line of every polar stack that crosses
+// the window; the tally is then added to HBM with one atomic per touched
+// FSR-group.  Waves take bundles of T consecutive lines of one stack (lane =
+// line x group) and walk the window's segments in lockstep.  A line's angular
+// flux is carried from window to window in its own boundary slot (read once
+// at its start, then free); a line starting on a vacuum face starts from 0.
+constexpr int kWinThreads = 512;
+constexpr int kWinWaves = kWinThreads / 64;
+constexpr int kMaxPolar = 64;
+constexpr size_t kWinFixedLds = 2048;   // reductions + per-stack line ranges
+
+struct WinArgs {
+    SweepArgs s;
+    const int *work;          // work unit codes 2*t + dir (longest first)
+    const int *filt_n;        // test hook: only this polar stack per unit (or null)
+    const long long *filt_i0; // test hook: only lines [i0, i0+T) of it
+    int Sw;                   // 2D segments per window
+};
+
+template <typename R, typename B>
+__global__ __launch_bounds__(kWinThreads) void k_sweep_win(WinArgs wa) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const SweepArgs &a = wa.s;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int G = a.G, K = a.K, P = a.P, T = a.T;
+    const int KG = K * G;
+    const int Sw = wa.Sw;
+    int *r_lo = (int *)smem;                     // [kMaxPolar] first line in window
+    int *r_hi = r_lo + kMaxPolar;                // [kMaxPolar] last line in window
+    int *bpre = r_hi + kMaxPolar;                // [kMaxPolar+1] bundle prefix
+    double *acc_l = (double *)(smem + kWinFixedLds);          // [Sw*KG]
+    R *q_l = (R *)(acc_l + (size_t)Sw * KG);                   // [Sw*KG]
+
+    const int unit = blockIdx.x;
+    const int code = wa.work[unit];
+    const long long t = code >> 1;
+    const int dir = code & 1;
+    const int meta = a.t_meta[t];
+    const int az = meta & 0xffff;
+    const double Lt = a.t_len[t];
+    const int f0 = a.t_first[t], f1 = a.t_first[t + 1];
+    const int nwin = (f1 - f0 + Sw - 1) / Sw;
+    const int fn = wa.filt_n ? wa.filt_n[unit] : -1;
+    const long long fi0 = wa.filt_i0 ? wa.filt_i0[unit] : 0;
+    const R *sigt = (const R *)a.sigt;
+    const R *qhat = (const R *)a.qhat;
+    const int tr = lane / G;
+    const int g = lane - tr * G;
+
+    for (int i = tid; i < Sw * KG; i += kWinThreads) acc_l[i] = 0.0;
+
+    double s_in = 0.0, s_out = 0.0, leak = 0.0;
+    long long nseg = 0, link_err = 0;
+
+    for (int wi = 0; wi < nwin; ++wi) {
+        const int w = dir ? nwin - 1 - wi : wi;
+        const int k0 = f0 + w * Sw;
+        const int k1 = min(k0 + Sw, f1) - 1;
+        const int nsw = k1 - k0 + 1;
+        const double wa_ = a.seg_pos[k0];
+        const double wb_ = (k1 + 1 < f1) ? a.seg_pos[k1 + 1] : Lt;
+        // stage the reduced source of every FSR-group of the window
+        if (a.mode == 0) {
+            for (int i = tid; i < nsw * KG; i += kWinThreads) {
+                const int kk = i / KG;
+                q_l[i] = qhat[(size_t)a.seg_reg[k0 + kk] * KG + (i - kk * KG)];
+            }
+        }
+        // wave 0: which lines of each polar stack cross the window (a
+        // contiguous index range, since the line extents move monotonically
+        // with the line index), and the bundle prefix over stacks
+        if (wave == 0) {
+            int lo = 0, hi = -1;
+            const int n = lane;
+            if (n < P && (fn < 0 || fn == n)) {
+                const long long s = t * P + n;
+                const int cs = a.cnt[s];
+                const double c = a.cot[az * P + n];
+                // ls(i) < wb and le(i) > wa, both monotone in i
+                auto ls_lt = [&](int i) {
+                    double l0, l1;
+                    clip_line(line_base(a, s, i), c, Lt, a.H, l0, l1);
+                    return l0 < wb_;
+                };
+                auto le_gt = [&](int i) {
+                    double l0, l1;
+                    clip_line(line_base(a, s, i), c, Lt, a.H, l0, l1);
+                    return l1 > wa_;
+                };
+                // c > 0: ls_lt is false..true, le_gt true..false; c < 0 mirrored
+                int a0 = 0, a1 = cs;   // first true of the rising predicate
+                int b0 = -1, b1 = cs - 1;   // last true of the falling predicate
+                if (c > 0) {
+                    while (a0 < a1) { int m = (a0 + a1) >> 1; if (ls_lt(m)) a1 = m; else a0 = m + 1; }
+                    while (b0 < b1) { int m = (b0 + b1 + 1) >> 1; if (le_gt(m)) b0 = m; else b1 = m - 1; }
+                } else {
+                    while (a0 < a1) { int m = (a0 + a1) >> 1; if (le_gt(m)) a1 = m; else a0 = m + 1; }
+                    while (b0 < b1) { int m = (b0 + b1 + 1) >> 1; if (ls_lt(m)) b0 = m; else b1 = m - 1; }
+                }
+                lo = a0;
+                hi = b0;
+                if (fn >= 0) {
+                    lo = max(lo, (int)fi0);
+                    hi = min(hi, (int)fi0 + T - 1);
+                }
+            }
+            const int nb = (hi >= lo) ? (hi - lo + T) / T : 0;
+            // inclusive scan of bundle counts over the polar stacks
+            int sc = nb;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int v = __shfl_up(sc, o, 64);
+                if (lane >= o) sc += v;
+            }
+            if (lane < kMaxPolar) {
+                r_lo[lane] = lo;
+                r_hi[lane] = hi;
+                bpre[lane + 1] = sc;
+            }
+            if (lane == 0) bpre[0] = 0;
+        }
+        __syncthreads();
+        const int total = bpre[P];
+        for (int bnd = wave; bnd < total; bnd += kWinWaves) {
+            int n = 0;
+            while (bpre[n + 1] <= bnd) ++n;
+            const long long s = t * P + n;
+            const int an = az * P + n;
+            const double c = a.cot[an], secl = a.secl[an], seca = a.seca[an], W = a.wgt[an];
+            const int i = r_lo[n] + (bnd - bpre[n]) * T + tr;
+            const bool active = (tr < T) && (i <= r_hi[n]);
+            const double base = line_base(a, s, i);
+            double ls = 0.0, le = 0.0;
+            clip_line(base, c, Lt, a.H, ls, le);
+            const bool starts = dir == 0 ? (ls >= wa_) : (le <= wb_);
+            const bool ends = dir == 0 ? (le <= wb_) : (ls >= wa_);
+            const long long slot = 2 * (a.trk_off[s] + i) + dir;
+            R psi = 0;
+            if (active && a.mode == 0) {
+                if (!starts) {
+                    psi = (R)((const B *)a.psi_in)[slot * G + g];
+                } else {
+                    if (a.psi_entry) psi = (R)a.psi_entry[(size_t)unit * 64 + (i - fi0) * G + g];
+                    else if (!is_vacuum(a, boundary_of(base, c, Lt, a.H, dir, false, meta)))
+                        psi = (R)((const B *)a.psi_in)[slot * G + g];
+                    s_in += W * (double)psi;
+                }
+            }
+            const bool up = (c > 0) != (dir == 1);
+            for (int kk = 0; kk < nsw; ++kk) {
+                const int k = dir ? (k1 - kk) : (k0 + kk);
+                const double s0 = a.seg_pos[k];
+                const double s1 = (k + 1 < f1) ? a.seg_pos[k + 1] : Lt;
+                if (!active) continue;
+                const int lb = (k - k0) * KG + g;
+                if (a.mode == 1) {
+                    nseg += for_pieces(s0, s1, ls, le, base, c, a.h, K, secl, seca, up,
+                                       [&](int kz, double l3) {
+                                           if (g == 0)
+                                               __hip_atomic_fetch_add(&acc_l[lb + kz * G], W * l3 / kFourPi,
+                                                                      __ATOMIC_RELAXED,
+                                                                      __HIP_MEMORY_SCOPE_WORKGROUP);
+                                       });
+                    continue;
+                }
+                const R st = sigt[a.reg_mat[a.seg_reg[k]] * G + g];
+                nseg += for_pieces(s0, s1, ls, le, base, c, a.h, K, secl, seca, up,
+                                   [&](int kz, double l3) {
+                                       const int li = lb + kz * G;
+                                       const R d = (psi - q_l[li]) *
+                                                   one_minus_exp<R>(st * (R)l3, a.exp_mode);   // Eq. 3
+                                       psi -= d;
+                                       __hip_atomic_fetch_add(&acc_l[li], W * (double)d, __ATOMIC_RELAXED,
+                                                              __HIP_MEMORY_SCOPE_WORKGROUP);
+                                   });
+            }
+            if (active && a.mode == 0) {
+                if (!ends) {
+                    ((B *)a.psi_in)[slot * G + g] = (B)psi;        // carried to the next window
+                } else {
+                    s_out += W * (double)psi;
+                    if (a.psi_exit) a.psi_exit[(size_t)unit * 64 + (i - fi0) * G + g] = (double)psi;
+                    const Bound b = boundary_of(base, c, Lt, a.H, dir, true, meta);
+                    if (is_vacuum(a, b)) {
+                        leak += W * (double)psi;
+                    } else if (a.psi_out) {
+                        const long long slot2 = successor_slot(a, b, t, (int)n, dir, base, c);
+                        if (slot2 >= 0) ((B *)a.psi_out)[slot2 * G + g] = (B)psi;
+                        else {
+                            ++link_err;
+                            leak += W * (double)psi;
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // flush the window tally: one HBM atomic per touched FSR-group (the
+        // volume tally has one entry per FSR, kept in the g = 0 slots)
+        for (int i = tid; i < nsw * KG; i += kWinThreads) {
+            const double v = acc_l[i];
+            if (v != 0.0) {
+                const int kk = i / KG;
+                const int rem = i - kk * KG;
+                const size_t reg = (size_t)a.seg_reg[k0 + kk];
+                if (a.mode == 0) unsafeAtomicAdd(&a.acc[reg * KG + rem], v);
+                else unsafeAtomicAdd(&a.acc[reg * K + rem / G], v);
+                acc_l[i] = 0.0;
+            }
+        }
+    }
+    // per-wave totals -> spread scalar slots
+    const double v_in = wave_sum(s_in), v_out = wave_sum(s_out), v_lk = wave_sum(leak);
+    const long long ns = wave_sum_ll(a.mode == 1 ? (g == 0 ? nseg : 0) : nseg);
+    const long long le_ = wave_sum_ll(link_err);
+    if (lane == 0) {
+        const int sl = (int)(((long long)unit * kWinWaves + wave) % kSlots);
+        if (a.mode == 0) {
+            unsafeAtomicAdd(&a.scal[slot_index(Q_SIN, sl)], v_in);
+            unsafeAtomicAdd(&a.scal[slot_index(Q_SOUT, sl)], v_out);
+            unsafeAtomicAdd(&a.scal[slot_index(Q_LEAK, sl)], v_lk);
+            if (le_) atomicAdd((unsigned long long *)&a.scal[slot_index(Q_LINKERR, sl)], (unsigned long long)le_);
+        }
+        atomicAdd((unsigned long long *)&a.scal[slot_index(Q_NSEG, sl)], (unsigned long long)ns);
+    }
+}
+
 // ------------------------------------------------------------------ trace hook
 
-// One thread per requested stored track (forward): the same per-2D-segment
-// axial splitting as the sweep, written out instead of swept.
+// One thread per requested stored track (forward): the same piece generation
+// as the sweeps, written out instead of swept.
 __global__ void k_trace(SweepArgs a, const long long *tracks, long long ntr, int cap, int *fsr,
                         double *len, int *count) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -320,39 +599,22 @@ __global__ void k_trace(SweepArgs a, const long long *tracks, long long ntr, int
     const double c = a.cot[an], secl = a.secl[an], seca = a.seca[an];
     const double Lt = a.t_len[t];
     const int f0 = a.t_first[t], f1 = a.t_first[t + 1];
-    const long long zi = trk - a.trk_off[s];
-    const double base = a.zeta[s] + (double)(a.ilo[s] + zi) * a.dz;
+    const double base = line_base(a, s, trk - a.trk_off[s]);
     double ls, le;
     clip_line(base, c, Lt, a.H, ls, le);
-    const bool up = c > 0;
     int m = 0;
     for (int k = seg_search(a.seg_pos, f0, f1, ls); k < f1; ++k) {
         const double s0 = a.seg_pos[k];
         if (s0 >= le) break;
         const double s1 = (k + 1 < f1) ? a.seg_pos[k + 1] : Lt;
-        const double sa = fmax(s0, ls), sb = fmin(s1, le);
-        if (!(sa < sb)) continue;
-        const double za = base + c * sa, zb = base + c * sb;
-        const double zlo = fmin(za, zb), zhi = fmax(za, zb);
-        int kl = (int)floor(zlo / a.h), kh = (int)ceil(zhi / a.h) - 1;
-        kl = min(max(kl, 0), K - 1);
-        kh = min(max(kh, kl), K - 1);
-        const int np = kh - kl + 1;
-        for (int p = 0; p < np; ++p) {
-            const int kz = up ? kl + p : kh - p;
-            double l3;
-            if (np == 1) l3 = (sb - sa) * secl;
-            else {
-                const double zl = fmax(zlo, kz * a.h), zh = fmin(zhi, (kz + 1) * a.h);
-                l3 = (zh - zl) * seca;
-            }
-            if (!(l3 >= kMinSeg)) continue;
+        const long long jb = (long long)a.seg_reg[k] * K;
+        for_pieces(s0, s1, ls, le, base, c, a.h, K, secl, seca, c > 0, [&](int kz, double l3) {
             if (m < cap) {
-                fsr[i * cap + m] = (int)((long long)a.seg_reg[k] * K + kz);
+                fsr[i * cap + m] = (int)(jb + kz);
                 len[i * cap + m] = l3;
             }
             ++m;
-        }
+        });
     }
     count[i] = m;
 }
@@ -555,6 +817,36 @@ int Solver::upload(const Plan &p) {
     HIPCHK(put(lay.off_sigt32, sigt32.data(), sigt32.size() * 4));
     HIPCHK(put(lay.off_sigt64, p.sigt.data(), p.sigt.size() * 8));
     HIPCHK(put(lay.off_sigs, p.sigs.data(), p.sigs.size() * 8));
+    // windowed sweep: window size from the LDS budget, and the work list of
+    // (2D track, direction) units ordered by decreasing work (lines x 2D
+    // segments), so the longest units start first
+    const size_t kg = (size_t)p.K * p.G;
+    const size_t budget = kWinLdsBudget - kWinFixedLds;
+    int max_seg = 1;
+    for (int64_t t = 0; t < p.n2d; ++t)
+        max_seg = std::max<int>(max_seg, (int)(p.seg_first[t + 1] - p.seg_first[t]));
+    sw32 = (int)std::min<size_t>(max_seg, budget / (kg * 12));
+    sw64 = (int)std::min<size_t>(max_seg, budget / (kg * 16));
+    if (p.P > kMaxPolar) sw32 = sw64 = 0;
+    std::vector<std::pair<double, int>> est(p.n2d);
+    for (int64_t t = 0; t < p.n2d; ++t) {
+        double lines = 0;
+        for (int n = 0; n < p.P; ++n) lines += (double)p.cnt[t * p.P + n];
+        est[t] = {lines * (double)(p.seg_first[t + 1] - p.seg_first[t]), (int)t};
+    }
+    std::stable_sort(est.begin(), est.end(), [](const std::pair<double, int> &x,
+                                                const std::pair<double, int> &y) {
+        return x.first > y.first;
+    });
+    std::vector<int> work(2 * p.n2d);
+    for (int64_t i = 0; i < p.n2d; ++i) {
+        work[2 * i] = 2 * est[i].second;
+        work[2 * i + 1] = 2 * est[i].second + 1;
+    }
+    HIPCHK(put(lay.off_work, work.data(), work.size() * 4));
+    chunk_off.assign(p.chunk_off.begin(), p.chunk_off.end());
+    trk_off.assign(p.trk_off.begin(), p.trk_off.end());
+    cnt.assign(p.cnt.begin(), p.cnt.end());
     HIPCHK(hipStreamSynchronize(stream));
     return MOC_OK;
 }
@@ -576,7 +868,29 @@ int Solver::compute_volumes() {
     return MOC_OK;
 }
 
-void Solver::launch_sweep(const SweepArgs &a, bool fp64) {
+void Solver::launch_sweep(SweepArgs a, bool fp64, const int *units, int n_units,
+                          const int *filt_n, const long long *filt_i0) {
+    const int sw = window_size(fp64);
+    if (sw >= 1) {
+        WinArgs wa;
+        wa.s = a;
+        wa.work = units ? units : ws_ptr<int>(ws, lay.off_work);
+        wa.filt_n = filt_n;
+        wa.filt_i0 = filt_i0;
+        wa.Sw = sw;
+        const unsigned nb = units ? (unsigned)n_units : (unsigned)(2 * info.n_2d_tracks);
+        if (nb == 0) return;
+        const size_t kg = (size_t)K * info.n_groups;
+        const size_t lds = kWinFixedLds + (size_t)sw * kg * (8 + (fp64 ? 8 : 4));
+        if (lay.psi64) {
+            if (fp64) k_sweep_win<double, double><<<nb, kWinThreads, lds, stream>>>(wa);
+            else k_sweep_win<float, double><<<nb, kWinThreads, lds, stream>>>(wa);
+        } else {
+            if (fp64) k_sweep_win<double, float><<<nb, kWinThreads, lds, stream>>>(wa);
+            else k_sweep_win<float, float><<<nb, kWinThreads, lds, stream>>>(wa);
+        }
+        return;
+    }
     const long long n = a.n_items;
     if (n <= 0) return;
     const int waves_per_block = 4;
@@ -687,7 +1001,7 @@ int Solver::sweep_items(long long n_items, const long long *items, const double 
                         const double *psi_in, int fp64, double *acc_out, double *psi_out) {
     const int G = info.n_groups, T = info.tracks_per_wave;
     const long long nfg = (long long)info.n_fsr * G;
-    // staging inside the workspace: items, entry and exit flux per (wave, lane)
+    // staging inside the workspace: items, entry and exit flux per (item, lane)
     const size_t cap = lay.n_item_cap;
     char *it_buf = ws + lay.off_items;
     double *entry = ws_ptr<double>(ws, lay.off_psi_entry);
@@ -698,27 +1012,52 @@ int Solver::sweep_items(long long n_items, const long long *items, const double 
     HIPCHK(hipMemcpyAsync(ws + lay.off_qhat32, q32.data(), nfg * 4, hipMemcpyHostToDevice, stream));
     int rc = fill_zero(ws + lay.off_acc, nfg * 8, stream);
     if (!rc) rc = fill_zero(ws + lay.off_scal, 128 * 1024, stream);
+    if (!rc) rc = fill_zero(ws + lay.off_psi0, lay.psi_bytes, stream);
     if (rc) return rc;
+    const bool windowed = window_size(fp64 != 0) >= 1;
     std::vector<double> ent, ex;
+    std::vector<int> units, fn;
+    std::vector<long long> fi0;
     for (long long b = 0; b < n_items; b += (long long)cap) {
         const long long nb = std::min<long long>(cap, n_items - b);
-        ent.assign(nb * 64, 0.0f);
+        ent.assign(nb * 64, 0.0);
         for (long long w = 0; w < nb; ++w)
             for (int tr = 0; tr < T; ++tr)
                 for (int g = 0; g < G; ++g)
                     ent[w * 64 + tr * G + g] = psi_in[((b + w) * T + tr) * G + g];
-        HIPCHK(hipMemcpyAsync(it_buf, items + b, nb * 8, hipMemcpyHostToDevice, stream));
         HIPCHK(hipMemcpyAsync(entry, ent.data(), nb * 64 * 8, hipMemcpyHostToDevice, stream));
         SweepArgs a = sweep_args(fp64, 0);
-        a.items = (const long long *)it_buf;
-        a.n_items = nb;
-        a.psi_in = nullptr;
+        a.psi_in = ws + lay.off_psi0;      // scratch for flux carried between windows
         a.psi_out = nullptr;
         a.psi_entry = entry;
         a.psi_exit = exitb;
-        launch_sweep(a, fp64 != 0);
+        if (windowed) {
+            // item (2*chunk + dir) -> unit (2D track, dir) restricted to the
+            // chunk's polar stack and lines
+            units.assign(nb, 0);
+            fn.assign(nb, 0);
+            fi0.assign(nb, 0);
+            for (long long w = 0; w < nb; ++w) {
+                const long long item = items[b + w], chunk = item >> 1;
+                const long long st = std::upper_bound(chunk_off.begin(), chunk_off.end(), chunk) -
+                                     chunk_off.begin() - 1;
+                units[w] = (int)(2 * (st / P) + (item & 1));
+                fn[w] = (int)(st % P);
+                fi0[w] = (chunk - chunk_off[st]) * T;
+            }
+            HIPCHK(hipMemcpyAsync(ws + lay.off_units, units.data(), nb * 4, hipMemcpyHostToDevice, stream));
+            HIPCHK(hipMemcpyAsync(ws + lay.off_filt_n, fn.data(), nb * 4, hipMemcpyHostToDevice, stream));
+            HIPCHK(hipMemcpyAsync(ws + lay.off_filt_i0, fi0.data(), nb * 8, hipMemcpyHostToDevice, stream));
+            launch_sweep(a, fp64 != 0, ws_ptr<int>(ws, lay.off_units), (int)nb,
+                         ws_ptr<int>(ws, lay.off_filt_n), ws_ptr<long long>(ws, lay.off_filt_i0));
+        } else {
+            HIPCHK(hipMemcpyAsync(it_buf, items + b, nb * 8, hipMemcpyHostToDevice, stream));
+            a.items = (const long long *)it_buf;
+            a.n_items = nb;
+            launch_sweep(a, fp64 != 0);
+        }
         HIPCHK(hipGetLastError());
-        ex.assign(nb * 64, 0.0f);
+        ex.assign(nb * 64, 0.0);
         HIPCHK(hipMemcpyAsync(ex.data(), exitb, nb * 64 * 8, hipMemcpyDeviceToHost, stream));
         HIPCHK(hipStreamSynchronize(stream));
         for (long long w = 0; w < nb; ++w)
@@ -728,7 +1067,7 @@ int Solver::sweep_items(long long n_items, const long long *items, const double 
     }
     HIPCHK(hipMemcpyAsync(acc_out, ws + lay.off_acc, nfg * 8, hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
-    return MOC_OK;
+    return reset();
 }
 
 int Solver::trace_tracks(long long n, const long long *ids, int cap, int *fsr, double *len,
