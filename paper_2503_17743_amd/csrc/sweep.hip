@@ -124,7 +124,7 @@ struct SweepArgs {
     long long n_items;
     long long n_stacks;
     double *scal;
-    double H, h, dz;
+    double H, h, inv_h, dz;
     int G, P, K, T;
     int bc[6];
     int exp_mode;
@@ -140,30 +140,27 @@ __device__ inline double line_base(const SweepArgs &a, long long s, long long i)
 // axial planes crossed by the line z = base + c l and call f(layer, length)
 // for each 3D segment in sweep order (up: moving towards +z).  A line that
 // stays in one layer over the segment has length ds / sin(theta) (Eq. 8); a
-// line crossing a whole layer has length h / |cos(theta)| (Eq. 11); partial
-// pieces at the ends use the same z-extent rule.
+// line crossing a whole layer has length h / |cos(theta)| (Eq. 11); the
+// partial pieces at the ends take their z-extent / |cos(theta)|.
 template <typename F>
 __device__ __forceinline__ int for_pieces(double s0, double s1, double ls, double le, double base,
-                                          double c, double h, int K, double secl, double seca,
-                                          bool up, F &&f) {
+                                          double c, double h, double inv_h, int K, double secl,
+                                          double seca, bool up, F &&f) {
     const double sa = fmax(s0, ls), sb = fmin(s1, le);
     if (!(sa < sb)) return 0;
     const double za = base + c * sa, zb = base + c * sb;
     const double zlo = fmin(za, zb), zhi = fmax(za, zb);
-    int kl = (int)floor(zlo / h), kh = (int)ceil(zhi / h) - 1;
+    int kl = (int)floor(zlo * inv_h), kh = (int)ceil(zhi * inv_h) - 1;
     kl = min(max(kl, 0), K - 1);
     kh = min(max(kh, kl), K - 1);
     const int np = kh - kl + 1;
+    const double l_bot = np == 1 ? (sb - sa) * secl : ((kl + 1) * h - zlo) * seca;
+    const double l_top = (zhi - kh * h) * seca;
+    const double l_mid = h * seca;
     int m = 0;
     for (int p = 0; p < np; ++p) {
         const int kz = up ? kl + p : kh - p;
-        double l3;
-        if (np == 1) {
-            l3 = (sb - sa) * secl;
-        } else {
-            const double zl = fmax(zlo, kz * h), zh = fmin(zhi, (kz + 1) * h);
-            l3 = (zh - zl) * seca;
-        }
+        const double l3 = kz == kl ? l_bot : (kz == kh ? l_top : l_mid);
         if (!(l3 >= kMinSeg)) continue;
         f(kz, l3);
         ++m;
@@ -295,7 +292,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
         if (!active) continue;
         const long long jb = (long long)reg * K;
         const R st = sigt[a.reg_mat[reg] * G + g];
-        nseg += for_pieces(s0, s1, ls, le, base, c, a.h, K, secl, seca, up, [&](int kz, double l3) {
+        nseg += for_pieces(s0, s1, ls, le, base, c, a.h, a.inv_h, K, secl, seca, up, [&](int kz, double l3) {
             const long long j = jb + kz;
             if (a.mode == 1) {
                 if (g == 0) unsafeAtomicAdd(&a.acc[j], W * l3 / kFourPi);
@@ -359,7 +356,14 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
 constexpr int kWinThreads = 512;
 constexpr int kWinWaves = kWinThreads / 64;
 constexpr int kMaxPolar = 64;
-constexpr size_t kWinFixedLds = 2048;   // reductions + per-stack line ranges
+constexpr size_t kWinFixedLds = 2048;   // per-stack line ranges and bundle prefix
+
+// Dynamic LDS of a window of Sw segments (see k_sweep_win for the layout).
+__host__ __device__ inline size_t win_lds_bytes(int Sw, int K, int G, int rbytes) {
+    const size_t kg = (size_t)K * G;
+    return kWinFixedLds + (size_t)Sw * kg * 8 + ((size_t)Sw + 1) * 8 + (size_t)Sw * kg * rbytes +
+           (size_t)Sw * G * rbytes + (size_t)Sw * 4 + 16;
+}
 
 struct WinArgs {
     SweepArgs s;
@@ -369,19 +373,28 @@ struct WinArgs {
     int Sw;                   // 2D segments per window
 };
 
-template <typename R, typename B>
+__device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// MODE 0: transport sweep; MODE 1: volume tally (W l / 4 pi per FSR).
+// EXPM 0: stable 1 - e^-tau; EXPM 1: 1 - hardware exp (precision study).
+template <typename R, typename B, int MODE, int EXPM>
 __global__ __launch_bounds__(kWinThreads) void k_sweep_win(WinArgs wa) {
     extern __shared__ __align__(16) unsigned char smem[];
     const SweepArgs &a = wa.s;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6);
     const int G = a.G, K = a.K, P = a.P, T = a.T;
     const int KG = K * G;
     const int Sw = wa.Sw;
-    int *r_lo = (int *)smem;                     // [kMaxPolar] first line in window
-    int *r_hi = r_lo + kMaxPolar;                // [kMaxPolar] last line in window
-    int *bpre = r_hi + kMaxPolar;                // [kMaxPolar+1] bundle prefix
-    double *acc_l = (double *)(smem + kWinFixedLds);          // [Sw*KG]
-    R *q_l = (R *)(acc_l + (size_t)Sw * KG);                   // [Sw*KG]
+    // LDS: [line ranges | FP64 tally Sw*KG | segment starts Sw+1 |
+    //       reduced source Sw*KG | Sigma_t Sw*G | region Sw]
+    int *r_lo = (int *)smem;
+    int *r_hi = r_lo + kMaxPolar;
+    int *bpre = r_hi + kMaxPolar;
+    double *acc_l = (double *)(smem + kWinFixedLds);
+    double *s_pos = acc_l + (size_t)Sw * KG;
+    R *q_l = (R *)(s_pos + Sw + 1);
+    R *s_st = q_l + (size_t)Sw * KG;
+    int *s_reg = (int *)(s_st + (size_t)Sw * G);
 
     const int unit = blockIdx.x;
     const int code = wa.work[unit];
@@ -407,20 +420,29 @@ __global__ __launch_bounds__(kWinThreads) void k_sweep_win(WinArgs wa) {
     for (int wi = 0; wi < nwin; ++wi) {
         const int w = dir ? nwin - 1 - wi : wi;
         const int k0 = f0 + w * Sw;
-        const int k1 = min(k0 + Sw, f1) - 1;
-        const int nsw = k1 - k0 + 1;
+        const int nsw = min(k0 + Sw, f1) - k0;
         const double wa_ = a.seg_pos[k0];
-        const double wb_ = (k1 + 1 < f1) ? a.seg_pos[k1 + 1] : Lt;
-        // stage the reduced source of every FSR-group of the window
-        if (a.mode == 0) {
+        const double wb_ = (k0 + nsw < f1) ? a.seg_pos[k0 + nsw] : Lt;
+        // stage the window: segment starts, regions, Sigma_t and the reduced
+        // source of every FSR-group the window can touch
+        for (int i = tid; i < nsw; i += kWinThreads) {
+            s_pos[i] = a.seg_pos[k0 + i];
+            s_reg[i] = a.seg_reg[k0 + i];
+        }
+        if (tid == 0) s_pos[nsw] = wb_;
+        if (MODE == 0) {
+            for (int i = tid; i < nsw * G; i += kWinThreads) {
+                const int kk = i / G;
+                s_st[i] = sigt[a.reg_mat[a.seg_reg[k0 + kk]] * G + (i - kk * G)];
+            }
             for (int i = tid; i < nsw * KG; i += kWinThreads) {
                 const int kk = i / KG;
                 q_l[i] = qhat[(size_t)a.seg_reg[k0 + kk] * KG + (i - kk * KG)];
             }
         }
         // wave 0: which lines of each polar stack cross the window (a
-        // contiguous index range, since the line extents move monotonically
-        // with the line index), and the bundle prefix over stacks
+        // contiguous index range, since line extents move monotonically with
+        // the line index), and the bundle prefix over the stacks
         if (wave == 0) {
             int lo = 0, hi = -1;
             const int n = lane;
@@ -428,7 +450,6 @@ __global__ __launch_bounds__(kWinThreads) void k_sweep_win(WinArgs wa) {
                 const long long s = t * P + n;
                 const int cs = a.cnt[s];
                 const double c = a.cot[az * P + n];
-                // ls(i) < wb and le(i) > wa, both monotone in i
                 auto ls_lt = [&](int i) {
                     double l0, l1;
                     clip_line(line_base(a, s, i), c, Lt, a.H, l0, l1);
@@ -439,8 +460,7 @@ __global__ __launch_bounds__(kWinThreads) void k_sweep_win(WinArgs wa) {
                     clip_line(line_base(a, s, i), c, Lt, a.H, l0, l1);
                     return l1 > wa_;
                 };
-                // c > 0: ls_lt is false..true, le_gt true..false; c < 0 mirrored
-                int a0 = 0, a1 = cs;   // first true of the rising predicate
+                int a0 = 0, a1 = cs;        // first true of the rising predicate
                 int b0 = -1, b1 = cs - 1;   // last true of the falling predicate
                 if (c > 0) {
                     while (a0 < a1) { int m = (a0 + a1) >> 1; if (ls_lt(m)) a1 = m; else a0 = m + 1; }
@@ -457,17 +477,14 @@ __global__ __launch_bounds__(kWinThreads) void k_sweep_win(WinArgs wa) {
                 }
             }
             const int nb = (hi >= lo) ? (hi - lo + T) / T : 0;
-            // inclusive scan of bundle counts over the polar stacks
             int sc = nb;
             for (int o = 1; o < 64; o <<= 1) {
                 const int v = __shfl_up(sc, o, 64);
                 if (lane >= o) sc += v;
             }
-            if (lane < kMaxPolar) {
-                r_lo[lane] = lo;
-                r_hi[lane] = hi;
-                bpre[lane + 1] = sc;
-            }
+            r_lo[lane] = lo;
+            r_hi[lane] = hi;
+            bpre[lane + 1] = sc;
             if (lane == 0) bpre[0] = 0;
         }
         __syncthreads();
@@ -475,19 +492,32 @@ __global__ __launch_bounds__(kWinThreads) void k_sweep_win(WinArgs wa) {
         for (int bnd = wave; bnd < total; bnd += kWinWaves) {
             int n = 0;
             while (bpre[n + 1] <= bnd) ++n;
+            n = uniform(n);
             const long long s = t * P + n;
             const int an = az * P + n;
             const double c = a.cot[an], secl = a.secl[an], seca = a.seca[an], W = a.wgt[an];
-            const int i = r_lo[n] + (bnd - bpre[n]) * T + tr;
+            const int i = uniform(r_lo[n] + (bnd - bpre[n]) * T) + tr;
             const bool active = (tr < T) && (i <= r_hi[n]);
             const double base = line_base(a, s, i);
-            double ls = 0.0, le = 0.0;
-            clip_line(base, c, Lt, a.H, ls, le);
+            double ls = 1e300, le = -1e300;
+            if (active) clip_line(base, c, Lt, a.H, ls, le);
+            // segments of the window touched by the bundle
+            const double u_lo = fmax(wave_min(ls), wa_), u_hi = fmin(wave_max(le), wb_);
+            int ka = 0, kb = nsw - 1;
+            {
+                int lo2 = 0, hi2 = nsw;
+                while (hi2 - lo2 > 1) { const int m = (lo2 + hi2) >> 1; if (s_pos[m] <= u_lo) lo2 = m; else hi2 = m; }
+                ka = lo2;
+                lo2 = ka;
+                hi2 = nsw;
+                while (hi2 - lo2 > 1) { const int m = (lo2 + hi2) >> 1; if (s_pos[m] < u_hi) lo2 = m; else hi2 = m; }
+                kb = lo2;
+            }
             const bool starts = dir == 0 ? (ls >= wa_) : (le <= wb_);
             const bool ends = dir == 0 ? (le <= wb_) : (ls >= wa_);
             const long long slot = 2 * (a.trk_off[s] + i) + dir;
             R psi = 0;
-            if (active && a.mode == 0) {
+            if (MODE == 0 && active) {
                 if (!starts) {
                     psi = (R)((const B *)a.psi_in)[slot * G + g];
                 } else {
@@ -498,14 +528,14 @@ __global__ __launch_bounds__(kWinThreads) void k_sweep_win(WinArgs wa) {
                 }
             }
             const bool up = (c > 0) != (dir == 1);
-            for (int kk = 0; kk < nsw; ++kk) {
-                const int k = dir ? (k1 - kk) : (k0 + kk);
-                const double s0 = a.seg_pos[k];
-                const double s1 = (k + 1 < f1) ? a.seg_pos[k + 1] : Lt;
+            const int nk = kb - ka + 1;
+            for (int q = 0; q < nk; ++q) {
+                const int kk = dir ? (kb - q) : (ka + q);
+                const double s0 = s_pos[kk], s1 = s_pos[kk + 1];
                 if (!active) continue;
-                const int lb = (k - k0) * KG + g;
-                if (a.mode == 1) {
-                    nseg += for_pieces(s0, s1, ls, le, base, c, a.h, K, secl, seca, up,
+                const int lb = kk * KG + g;
+                if (MODE == 1) {
+                    nseg += for_pieces(s0, s1, ls, le, base, c, a.h, a.inv_h, K, secl, seca, up,
                                        [&](int kz, double l3) {
                                            if (g == 0)
                                                __hip_atomic_fetch_add(&acc_l[lb + kz * G], W * l3 / kFourPi,
@@ -514,18 +544,17 @@ __global__ __launch_bounds__(kWinThreads) void k_sweep_win(WinArgs wa) {
                                        });
                     continue;
                 }
-                const R st = sigt[a.reg_mat[a.seg_reg[k]] * G + g];
-                nseg += for_pieces(s0, s1, ls, le, base, c, a.h, K, secl, seca, up,
+                const R st = s_st[kk * G + g];
+                nseg += for_pieces(s0, s1, ls, le, base, c, a.h, a.inv_h, K, secl, seca, up,
                                    [&](int kz, double l3) {
                                        const int li = lb + kz * G;
-                                       const R d = (psi - q_l[li]) *
-                                                   one_minus_exp<R>(st * (R)l3, a.exp_mode);   // Eq. 3
-                                       psi -= d;
+                                       const R d = (psi - q_l[li]) * one_minus_exp<R>(st * (R)l3, EXPM);
+                                       psi -= d;                                      // Eq. 3
                                        __hip_atomic_fetch_add(&acc_l[li], W * (double)d, __ATOMIC_RELAXED,
                                                               __HIP_MEMORY_SCOPE_WORKGROUP);
                                    });
             }
-            if (active && a.mode == 0) {
+            if (MODE == 0 && active) {
                 if (!ends) {
                     ((B *)a.psi_in)[slot * G + g] = (B)psi;        // carried to the next window
                 } else {
@@ -535,7 +564,7 @@ __global__ __launch_bounds__(kWinThreads) void k_sweep_win(WinArgs wa) {
                     if (is_vacuum(a, b)) {
                         leak += W * (double)psi;
                     } else if (a.psi_out) {
-                        const long long slot2 = successor_slot(a, b, t, (int)n, dir, base, c);
+                        const long long slot2 = successor_slot(a, b, t, n, dir, base, c);
                         if (slot2 >= 0) ((B *)a.psi_out)[slot2 * G + g] = (B)psi;
                         else {
                             ++link_err;
@@ -553,20 +582,21 @@ __global__ __launch_bounds__(kWinThreads) void k_sweep_win(WinArgs wa) {
             if (v != 0.0) {
                 const int kk = i / KG;
                 const int rem = i - kk * KG;
-                const size_t reg = (size_t)a.seg_reg[k0 + kk];
-                if (a.mode == 0) unsafeAtomicAdd(&a.acc[reg * KG + rem], v);
+                const size_t reg = (size_t)s_reg[kk];
+                if (MODE == 0) unsafeAtomicAdd(&a.acc[reg * KG + rem], v);
                 else unsafeAtomicAdd(&a.acc[reg * K + rem / G], v);
                 acc_l[i] = 0.0;
             }
         }
+        __syncthreads();
     }
     // per-wave totals -> spread scalar slots
     const double v_in = wave_sum(s_in), v_out = wave_sum(s_out), v_lk = wave_sum(leak);
-    const long long ns = wave_sum_ll(a.mode == 1 ? (g == 0 ? nseg : 0) : nseg);
+    const long long ns = wave_sum_ll(MODE == 1 ? (g == 0 ? nseg : 0) : nseg);
     const long long le_ = wave_sum_ll(link_err);
     if (lane == 0) {
         const int sl = (int)(((long long)unit * kWinWaves + wave) % kSlots);
-        if (a.mode == 0) {
+        if (MODE == 0) {
             unsafeAtomicAdd(&a.scal[slot_index(Q_SIN, sl)], v_in);
             unsafeAtomicAdd(&a.scal[slot_index(Q_SOUT, sl)], v_out);
             unsafeAtomicAdd(&a.scal[slot_index(Q_LEAK, sl)], v_lk);
@@ -608,7 +638,7 @@ __global__ void k_trace(SweepArgs a, const long long *tracks, long long ntr, int
         if (s0 >= le) break;
         const double s1 = (k + 1 < f1) ? a.seg_pos[k + 1] : Lt;
         const long long jb = (long long)a.seg_reg[k] * K;
-        for_pieces(s0, s1, ls, le, base, c, a.h, K, secl, seca, c > 0, [&](int kz, double l3) {
+        for_pieces(s0, s1, ls, le, base, c, a.h, a.inv_h, K, secl, seca, c > 0, [&](int kz, double l3) {
             if (m < cap) {
                 fsr[i * cap + m] = (int)(jb + kz);
                 len[i * cap + m] = l3;
@@ -750,6 +780,7 @@ SweepArgs Solver::sweep_args(int fp64, int exp_mode) const {
     a.n_stacks = info.n_stacks;
     a.H = H;
     a.h = h;
+    a.inv_h = 1.0 / h;
     a.dz = info.dz;
     a.G = info.n_groups;
     a.P = P;
@@ -820,13 +851,16 @@ int Solver::upload(const Plan &p) {
     // windowed sweep: window size from the LDS budget, and the work list of
     // (2D track, direction) units ordered by decreasing work (lines x 2D
     // segments), so the longest units start first
-    const size_t kg = (size_t)p.K * p.G;
-    const size_t budget = kWinLdsBudget - kWinFixedLds;
     int max_seg = 1;
     for (int64_t t = 0; t < p.n2d; ++t)
         max_seg = std::max<int>(max_seg, (int)(p.seg_first[t + 1] - p.seg_first[t]));
-    sw32 = (int)std::min<size_t>(max_seg, budget / (kg * 12));
-    sw64 = (int)std::min<size_t>(max_seg, budget / (kg * 16));
+    auto fit = [&](int rbytes) {
+        int sw = 0;
+        while (sw < max_seg && win_lds_bytes(sw + 1, p.K, p.G, rbytes) <= kWinLdsBudget) ++sw;
+        return sw;
+    };
+    sw32 = fit(4);
+    sw64 = fit(8);
     if (p.P > kMaxPolar) sw32 = sw64 = 0;
     std::vector<std::pair<double, int>> est(p.n2d);
     for (int64_t t = 0; t < p.n2d; ++t) {
@@ -868,6 +902,13 @@ int Solver::compute_volumes() {
     return MOC_OK;
 }
 
+template <typename R, typename B>
+static void launch_win(const WinArgs &wa, unsigned nb, size_t lds, hipStream_t st, int mode, int expm) {
+    if (mode == 1) k_sweep_win<R, B, 1, 0><<<nb, kWinThreads, lds, st>>>(wa);
+    else if (expm == 0) k_sweep_win<R, B, 0, 0><<<nb, kWinThreads, lds, st>>>(wa);
+    else k_sweep_win<R, B, 0, 1><<<nb, kWinThreads, lds, st>>>(wa);
+}
+
 void Solver::launch_sweep(SweepArgs a, bool fp64, const int *units, int n_units,
                           const int *filt_n, const long long *filt_i0) {
     const int sw = window_size(fp64);
@@ -880,14 +921,13 @@ void Solver::launch_sweep(SweepArgs a, bool fp64, const int *units, int n_units,
         wa.Sw = sw;
         const unsigned nb = units ? (unsigned)n_units : (unsigned)(2 * info.n_2d_tracks);
         if (nb == 0) return;
-        const size_t kg = (size_t)K * info.n_groups;
-        const size_t lds = kWinFixedLds + (size_t)sw * kg * (8 + (fp64 ? 8 : 4));
+        const size_t lds = win_lds_bytes(sw, K, info.n_groups, fp64 ? 8 : 4);
         if (lay.psi64) {
-            if (fp64) k_sweep_win<double, double><<<nb, kWinThreads, lds, stream>>>(wa);
-            else k_sweep_win<float, double><<<nb, kWinThreads, lds, stream>>>(wa);
+            if (fp64) launch_win<double, double>(wa, nb, lds, stream, a.mode, a.exp_mode);
+            else launch_win<float, double>(wa, nb, lds, stream, a.mode, a.exp_mode);
         } else {
-            if (fp64) k_sweep_win<double, float><<<nb, kWinThreads, lds, stream>>>(wa);
-            else k_sweep_win<float, float><<<nb, kWinThreads, lds, stream>>>(wa);
+            if (fp64) launch_win<double, float>(wa, nb, lds, stream, a.mode, a.exp_mode);
+            else launch_win<float, float>(wa, nb, lds, stream, a.mode, a.exp_mode);
         }
         return;
     }
