@@ -74,6 +74,8 @@ def main():
     ap.add_argument("--workload", default="lattice8")
     ap.add_argument("--oracle-iters", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the sweep is single-GPU in this build "
@@ -86,6 +88,14 @@ def main():
 
     prob = P.get(args.workload)
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        # a plain copy of known size: reads 1 GiB and writes 1 GiB of HBM
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     plan = moc.Plan(prob)
     solver = moc.Solver(plan, fp64_boundary=False)
     solver.set_source(prob.q)
@@ -102,7 +112,8 @@ def main():
         parity = float(np.max(np.abs(gphi - ophi) / np.maximum(np.abs(ophi), 1e-300)))
 
     solver.reset()
-    solver.iterate(args.warmup, stats=False)
+    if args.warmup > 0:
+        solver.iterate(args.warmup, stats=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st = solver.iterate(args.steps, stats=True)

@@ -42,14 +42,28 @@ __host__ __device__ inline size_t slot_index(int q, int slot) {
 
 // ------------------------------------------------------------------ helpers
 
+// F(tau) = 1 - e^{-tau} for tau >= 0 without cancellation: below tau = 1/2
+// F = tau p(tau), with p the degree-5 Chebyshev interpolant of (1 - e^-t)/t on
+// [0, 1/2] (max relative error of F 1.5 ulp in FP32); above it the hardware
+// exp2 is used, where 1 - e^-tau >= 0.39 limits the cancellation (about 3 ulp).
+__device__ inline float one_minus_exp_f32(float t) {
+    float p = -1.1237151e-3f;
+    p = fmaf(p, t, 8.1900032e-3f);
+    p = fmaf(p, t, -4.1630242e-2f);
+    p = fmaf(p, t, 1.6666245e-1f);
+    p = fmaf(p, t, -4.9999982e-1f);
+    p = fmaf(p, t, 1.0f);
+    const float large = 1.0f - __builtin_amdgcn_exp2f(t * -1.44269504088896341f);
+    return t < 0.5f ? t * p : large;
+}
+
 template <typename R>
 __device__ inline R one_minus_exp(R tau, int exp_mode);
 
 template <>
 __device__ inline float one_minus_exp<float>(float tau, int exp_mode) {
-    // stable 1 - e^{-tau}: expm1 keeps full relative accuracy for small tau
-    if (exp_mode == 0) return -expm1f(-tau);
-    return 1.0f - __expf(-tau);
+    if (exp_mode == 0) return one_minus_exp_f32(tau);
+    return 1.0f - __expf(-tau);      // naive form, precision study only
 }
 template <>
 __device__ inline double one_minus_exp<double>(double tau, int) {
@@ -136,34 +150,58 @@ __device__ inline double line_base(const SweepArgs &a, long long s, long long i)
     return a.zeta[s] + (double)(a.ilo[s] + i) * a.dz;
 }
 
-// Split the part [max(s0,ls), min(s1,le)] of the 2D segment [s0,s1] at the
-// axial planes crossed by the line z = base + c l and call f(layer, length)
-// for each 3D segment in sweep order (up: moving towards +z).  A line that
-// stays in one layer over the segment has length ds / sin(theta) (Eq. 8); a
-// line crossing a whole layer has length h / |cos(theta)| (Eq. 11); the
-// partial pieces at the ends take their z-extent / |cos(theta)|.
+// Incremental walk of one line through its 2D segments in sweep order.  The
+// line z = base + c l crosses the axial plane z = m h at l = m h/c - base/c;
+// between two consecutive crossings it stays in one layer, so a 2D segment
+// [s0, s1] splits into pieces at the crossings that fall inside it (Eqs. 6-7
+// locate them per FSR; here per line).  Each piece has 3D length
+// dl / sin(theta): a whole 2D segment inside one layer gives Eq. 8, a whole
+// layer crossed gives h / |cos(theta)| (Eq. 11).  Crossing positions are
+// evaluated directly, never accumulated, so no rounding drifts along a line.
+struct Walker {
+    double lcur;    // current 2D position
+    double lnp;     // 2D position of the next plane crossing in sweep order
+    double hc, bc;  // h / c and base / c
+    int k;          // current layer
+    int mnext;      // index of the next plane
+    int kstep;      // +1 moving up, -1 moving down
+};
+
+__device__ inline void walk_init(Walker &w, double base, double c, double h, double inv_h, int K,
+                                 double l0, bool bwd) {
+    const bool up = (c > 0) != bwd;
+    const double z0 = base + c * l0;
+    int k = up ? (int)floor(z0 * inv_h) : (int)ceil(z0 * inv_h) - 1;
+    k = min(max(k, 0), K - 1);
+    w.k = k;
+    w.kstep = up ? 1 : -1;
+    w.mnext = up ? k + 1 : k;
+    w.hc = h / c;
+    w.bc = base / c;
+    w.lcur = l0;
+    w.lnp = w.mnext * w.hc - w.bc;
+}
+
+// Walk from the current position to e (the end of this 2D segment in sweep
+// order) and call f(layer, length) for every piece of at least kMinSeg.
 template <typename F>
-__device__ __forceinline__ int for_pieces(double s0, double s1, double ls, double le, double base,
-                                          double c, double h, double inv_h, int K, double secl,
-                                          double seca, bool up, F &&f) {
-    const double sa = fmax(s0, ls), sb = fmin(s1, le);
-    if (!(sa < sb)) return 0;
-    const double za = base + c * sa, zb = base + c * sb;
-    const double zlo = fmin(za, zb), zhi = fmax(za, zb);
-    int kl = (int)floor(zlo * inv_h), kh = (int)ceil(zhi * inv_h) - 1;
-    kl = min(max(kl, 0), K - 1);
-    kh = min(max(kh, kl), K - 1);
-    const int np = kh - kl + 1;
-    const double l_bot = np == 1 ? (sb - sa) * secl : ((kl + 1) * h - zlo) * seca;
-    const double l_top = (zhi - kh * h) * seca;
-    const double l_mid = h * seca;
+__device__ __forceinline__ int walk_segment(Walker &w, double e, double secl, int K, bool bwd,
+                                            F &&f) {
     int m = 0;
-    for (int p = 0; p < np; ++p) {
-        const int kz = up ? kl + p : kh - p;
-        const double l3 = kz == kl ? l_bot : (kz == kh ? l_top : l_mid);
-        if (!(l3 >= kMinSeg)) continue;
-        f(kz, l3);
-        ++m;
+    for (;;) {
+        const bool cross = bwd ? (w.lnp > e) : (w.lnp < e);
+        const double lend = cross ? w.lnp : e;
+        const double l3 = (bwd ? (w.lcur - lend) : (lend - w.lcur)) * secl;
+        const int kz = min(max(w.k, 0), K - 1);
+        if (l3 >= kMinSeg) {
+            f(kz, l3);
+            ++m;
+        }
+        w.lcur = lend;
+        if (!cross) break;
+        w.k += w.kstep;
+        w.mnext += w.kstep;
+        w.lnp = w.mnext * w.hc - w.bc;
     }
     return m;
 }
@@ -257,7 +295,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
     const int n = (int)(s - t * P);
     const int meta = a.t_meta[t];
     const int an = (meta & 0xffff) * P + n;
-    const double c = a.cot[an], secl = a.secl[an], seca = a.seca[an], W = a.wgt[an];
+    const double c = a.cot[an], secl = a.secl[an], W = a.wgt[an];
     const double Lt = a.t_len[t];
     const int f0 = a.t_first[t], f1 = a.t_first[t + 1];
     const int tr = lane / G;
@@ -282,7 +320,8 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
     long long nseg = 0;
     const int k_first = seg_search(a.seg_pos, f0, f1, l_lo);
     const int k_last = seg_search(a.seg_pos, f0, f1, l_hi);
-    const bool up = (c > 0) != (dir == 1);
+    Walker wk;
+    if (active) walk_init(wk, base, c, a.h, a.inv_h, K, dir ? le : ls, dir == 1);
     const int nk = k_last - k_first + 1;
     for (int kk = 0; kk < nk; ++kk) {
         const int k = dir ? (k_last - kk) : (k_first + kk);
@@ -290,9 +329,11 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
         const double s1 = (k + 1 < f1) ? a.seg_pos[k + 1] : Lt;
         const int reg = a.seg_reg[k];
         if (!active) continue;
+        const double e = dir ? fmax(s0, ls) : fmin(s1, le);
+        if (!(dir ? e < wk.lcur : e > wk.lcur)) continue;
         const long long jb = (long long)reg * K;
         const R st = sigt[a.reg_mat[reg] * G + g];
-        nseg += for_pieces(s0, s1, ls, le, base, c, a.h, a.inv_h, K, secl, seca, up, [&](int kz, double l3) {
+        nseg += walk_segment(wk, e, secl, K, dir == 1, [&](int kz, double l3) {
             const long long j = jb + kz;
             if (a.mode == 1) {
                 if (g == 0) unsafeAtomicAdd(&a.acc[j], W * l3 / kFourPi);
@@ -495,7 +536,7 @@ __global__ __launch_bounds__(kWinThreads) void k_sweep_win(WinArgs wa) {
             n = uniform(n);
             const long long s = t * P + n;
             const int an = az * P + n;
-            const double c = a.cot[an], secl = a.secl[an], seca = a.seca[an], W = a.wgt[an];
+            const double c = a.cot[an], secl = a.secl[an], W = a.wgt[an];
             const int i = uniform(r_lo[n] + (bnd - bpre[n]) * T) + tr;
             const bool active = (tr < T) && (i <= r_hi[n]);
             const double base = line_base(a, s, i);
@@ -527,32 +568,32 @@ __global__ __launch_bounds__(kWinThreads) void k_sweep_win(WinArgs wa) {
                     s_in += W * (double)psi;
                 }
             }
-            const bool up = (c > 0) != (dir == 1);
+            Walker wk;
+            if (active) walk_init(wk, base, c, a.h, a.inv_h, K, dir ? fmin(le, wb_) : fmax(ls, wa_), dir == 1);
             const int nk = kb - ka + 1;
             for (int q = 0; q < nk; ++q) {
                 const int kk = dir ? (kb - q) : (ka + q);
                 const double s0 = s_pos[kk], s1 = s_pos[kk + 1];
                 if (!active) continue;
+                const double e = dir ? fmax(s0, ls) : fmin(s1, le);
+                if (!(dir ? e < wk.lcur : e > wk.lcur)) continue;
                 const int lb = kk * KG + g;
                 if (MODE == 1) {
-                    nseg += for_pieces(s0, s1, ls, le, base, c, a.h, a.inv_h, K, secl, seca, up,
-                                       [&](int kz, double l3) {
-                                           if (g == 0)
-                                               __hip_atomic_fetch_add(&acc_l[lb + kz * G], W * l3 / kFourPi,
-                                                                      __ATOMIC_RELAXED,
-                                                                      __HIP_MEMORY_SCOPE_WORKGROUP);
-                                       });
+                    nseg += walk_segment(wk, e, secl, K, dir == 1, [&](int kz, double l3) {
+                        if (g == 0)
+                            __hip_atomic_fetch_add(&acc_l[lb + kz * G], W * l3 / kFourPi, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+                    });
                     continue;
                 }
                 const R st = s_st[kk * G + g];
-                nseg += for_pieces(s0, s1, ls, le, base, c, a.h, a.inv_h, K, secl, seca, up,
-                                   [&](int kz, double l3) {
-                                       const int li = lb + kz * G;
-                                       const R d = (psi - q_l[li]) * one_minus_exp<R>(st * (R)l3, EXPM);
-                                       psi -= d;                                      // Eq. 3
-                                       __hip_atomic_fetch_add(&acc_l[li], W * (double)d, __ATOMIC_RELAXED,
-                                                              __HIP_MEMORY_SCOPE_WORKGROUP);
-                                   });
+                nseg += walk_segment(wk, e, secl, K, dir == 1, [&](int kz, double l3) {
+                    const int li = lb + kz * G;
+                    const R d = (psi - q_l[li]) * one_minus_exp<R>(st * (R)l3, EXPM);
+                    psi -= d;                                                      // Eq. 3
+                    __hip_atomic_fetch_add(&acc_l[li], W * (double)d, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                });
             }
             if (MODE == 0 && active) {
                 if (!ends) {
@@ -626,19 +667,23 @@ __global__ void k_trace(SweepArgs a, const long long *tracks, long long ntr, int
     const long long t = s / P;
     const int n = (int)(s - t * P);
     const int an = (a.t_meta[t] & 0xffff) * P + n;
-    const double c = a.cot[an], secl = a.secl[an], seca = a.seca[an];
+    const double c = a.cot[an], secl = a.secl[an];
     const double Lt = a.t_len[t];
     const int f0 = a.t_first[t], f1 = a.t_first[t + 1];
     const double base = line_base(a, s, trk - a.trk_off[s]);
     double ls, le;
     clip_line(base, c, Lt, a.H, ls, le);
+    Walker wk;
+    walk_init(wk, base, c, a.h, a.inv_h, K, ls, false);
     int m = 0;
     for (int k = seg_search(a.seg_pos, f0, f1, ls); k < f1; ++k) {
         const double s0 = a.seg_pos[k];
         if (s0 >= le) break;
         const double s1 = (k + 1 < f1) ? a.seg_pos[k + 1] : Lt;
+        const double e = fmin(s1, le);
+        if (!(e > wk.lcur)) continue;
         const long long jb = (long long)a.seg_reg[k] * K;
-        for_pieces(s0, s1, ls, le, base, c, a.h, a.inv_h, K, secl, seca, c > 0, [&](int kz, double l3) {
+        walk_segment(wk, e, secl, K, false, [&](int kz, double l3) {
             if (m < cap) {
                 fsr[i * cap + m] = (int)(jb + kz);
                 len[i * cap + m] = l3;

@@ -90,7 +90,7 @@ def test_traced_segments_match_oracle(moc, nthreads, case):
         fo, lo = om.trace(tr)
         assert n == len(fo), tr
         np.testing.assert_array_equal(f, fo)
-        np.testing.assert_allclose(l, lo, rtol=1e-11, atol=1e-13)
+        np.testing.assert_allclose(l, lo, rtol=1e-11, atol=1e-12)
 
 
 @pytest.mark.parametrize("fp64", [False, True])
