@@ -183,20 +183,19 @@ __device__ inline void walk_init(Walker &w, double base, double c, double h, dou
 }
 
 // Walk from the current position to e (the end of this 2D segment in sweep
-// order) and call f(layer, length) for every piece of at least kMinSeg.
-template <typename F>
-__device__ __forceinline__ int walk_segment(Walker &w, double e, double secl, int K, bool bwd,
-                                            F &&f) {
+// order) and call f(layer, length, valid) for every piece; valid is false for
+// pieces shorter than kMinSeg (the caller adds nothing for them).  Returns
+// the number of valid pieces.
+template <bool BWD, typename F>
+__device__ __forceinline__ int walk_segment(Walker &w, double e, double secl, int K, F &&f) {
     int m = 0;
     for (;;) {
-        const bool cross = bwd ? (w.lnp > e) : (w.lnp < e);
+        const bool cross = BWD ? (w.lnp > e) : (w.lnp < e);
         const double lend = cross ? w.lnp : e;
-        const double l3 = (bwd ? (w.lcur - lend) : (lend - w.lcur)) * secl;
-        const int kz = min(max(w.k, 0), K - 1);
-        if (l3 >= kMinSeg) {
-            f(kz, l3);
-            ++m;
-        }
+        const double l3 = (BWD ? (w.lcur - lend) : (lend - w.lcur)) * secl;
+        const bool valid = l3 >= kMinSeg;
+        f(min(max(w.k, 0), K - 1), l3, valid);
+        m += valid;
         w.lcur = lend;
         if (!cross) break;
         w.k += w.kstep;
@@ -333,7 +332,8 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
         if (!(dir ? e < wk.lcur : e > wk.lcur)) continue;
         const long long jb = (long long)reg * K;
         const R st = sigt[a.reg_mat[reg] * G + g];
-        nseg += walk_segment(wk, e, secl, K, dir == 1, [&](int kz, double l3) {
+        auto piece = [&](int kz, double l3, bool valid) {
+            if (!valid) return;
             const long long j = jb + kz;
             if (a.mode == 1) {
                 if (g == 0) unsafeAtomicAdd(&a.acc[j], W * l3 / kFourPi);
@@ -343,7 +343,8 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
             const R d = (psi - q) * one_minus_exp<R>(st * (R)l3, a.exp_mode);   // Eq. 3
             psi -= d;
             unsafeAtomicAdd(&a.acc[j * G + g], W * (double)d);
-        });
+        };
+        nseg += dir ? walk_segment<true>(wk, e, secl, K, piece) : walk_segment<false>(wk, e, secl, K, piece);
     }
     if (a.mode == 1) {
         const long long tot = wave_sum_ll(active && g == 0 ? nseg : 0);
@@ -418,9 +419,8 @@ __device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v);
 
 // MODE 0: transport sweep; MODE 1: volume tally (W l / 4 pi per FSR).
 // EXPM 0: stable 1 - e^-tau; EXPM 1: 1 - hardware exp (precision study).
-template <typename R, typename B, int MODE, int EXPM>
-__global__ __launch_bounds__(kWinThreads) void k_sweep_win(WinArgs wa) {
-    extern __shared__ __align__(16) unsigned char smem[];
+template <typename R, typename B, int MODE, int EXPM, bool BWD>
+__device__ __forceinline__ void sweep_unit(const WinArgs &wa, unsigned char *smem) {
     const SweepArgs &a = wa.s;
     const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6);
     const int G = a.G, K = a.K, P = a.P, T = a.T;
@@ -440,7 +440,7 @@ __global__ __launch_bounds__(kWinThreads) void k_sweep_win(WinArgs wa) {
     const int unit = blockIdx.x;
     const int code = wa.work[unit];
     const long long t = code >> 1;
-    const int dir = code & 1;
+    constexpr int dir = BWD ? 1 : 0;
     const int meta = a.t_meta[t];
     const int az = meta & 0xffff;
     const double Lt = a.t_len[t];
@@ -579,17 +579,19 @@ __global__ __launch_bounds__(kWinThreads) void k_sweep_win(WinArgs wa) {
                 if (!(dir ? e < wk.lcur : e > wk.lcur)) continue;
                 const int lb = kk * KG + g;
                 if (MODE == 1) {
-                    nseg += walk_segment(wk, e, secl, K, dir == 1, [&](int kz, double l3) {
-                        if (g == 0)
+                    nseg += walk_segment<BWD>(wk, e, secl, K, [&](int kz, double l3, bool valid) {
+                        if (g == 0 && valid)
                             __hip_atomic_fetch_add(&acc_l[lb + kz * G], W * l3 / kFourPi, __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_WORKGROUP);
                     });
                     continue;
                 }
                 const R st = s_st[kk * G + g];
-                nseg += walk_segment(wk, e, secl, K, dir == 1, [&](int kz, double l3) {
+                nseg += walk_segment<BWD>(wk, e, secl, K, [&](int kz, double l3, bool valid) {
                     const int li = lb + kz * G;
-                    const R d = (psi - q_l[li]) * one_minus_exp<R>(st * (R)l3, EXPM);
+                    // a piece below kMinSeg adds nothing: F = 0 keeps psi unchanged
+                    const R F = valid ? one_minus_exp<R>(st * (R)l3, EXPM) : (R)0;
+                    const R d = (psi - q_l[li]) * F;
                     psi -= d;                                                      // Eq. 3
                     __hip_atomic_fetch_add(&acc_l[li], W * (double)d, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -647,6 +649,14 @@ __global__ __launch_bounds__(kWinThreads) void k_sweep_win(WinArgs wa) {
     }
 }
 
+template <typename R, typename B, int MODE, int EXPM>
+__global__ __launch_bounds__(kWinThreads) void k_sweep_win(WinArgs wa) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    // the direction is uniform per workgroup: specialise the whole unit on it
+    if (wa.work[blockIdx.x] & 1) sweep_unit<R, B, MODE, EXPM, true>(wa, smem);
+    else sweep_unit<R, B, MODE, EXPM, false>(wa, smem);
+}
+
 // ------------------------------------------------------------------ trace hook
 
 // One thread per requested stored track (forward): the same piece generation
@@ -683,7 +693,8 @@ __global__ void k_trace(SweepArgs a, const long long *tracks, long long ntr, int
         const double e = fmin(s1, le);
         if (!(e > wk.lcur)) continue;
         const long long jb = (long long)a.seg_reg[k] * K;
-        walk_segment(wk, e, secl, K, false, [&](int kz, double l3) {
+        walk_segment<false>(wk, e, secl, K, [&](int kz, double l3, bool valid) {
+            if (!valid) return;
             if (m < cap) {
                 fsr[i * cap + m] = (int)(jb + kz);
                 len[i * cap + m] = l3;
