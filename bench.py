@@ -66,6 +66,53 @@ def cpu_baseline(prob, iters, threads):
     }
 
 
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def max_rel(a, b):
+    import numpy as np
+    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300)))
+
+
+def serving_bench(n_requests, arena_gib, tol=1e-6, max_iters=400, load=0.8):
+    """Continuous batching against one-at-a-time on the same requests: first
+    all arriving at once (throughput), then Poisson arrivals at `load` times
+    the one-at-a-time service rate (latency)."""
+    from paper_2503_17743_amd import moc, problems as P, serve as S
+    probs = [r.problem for r in P.serving_stream(n_requests=n_requests)]
+    reqs = P.with_arrivals(probs, None)
+    plans = S.plan_requests(reqs)
+    arena = moc.Server.overhead_bytes(64) + int(arena_gib * (1 << 30))
+    log(f"serving: {n_requests} requests, one at a time ...")
+    phi_seq, seq = S.one_at_a_time(reqs, plans, tol, max_iters)
+    log(f"serving: one at a time {seq['wall_s']:.2f} s; batched ...")
+    phi_bat, bat = S.run_stream(reqs, plans, tol, max_iters, arena)
+    log(f"serving: batched {bat['wall_s']:.2f} s; Poisson arrivals ...")
+    err = max(max_rel(a, b) for a, b in zip(phi_bat, phi_seq))
+    conv = all(st["converged"] for st in bat["stats"]) and all(st["converged"] for st in seq["stats"])
+    rate = load * n_requests / seq["wall_s"]
+    preqs = P.with_arrivals(probs, rate)
+    _, pseq = S.one_at_a_time(preqs, plans, tol, max_iters, use_arrivals=True)
+    log(f"serving: Poisson one at a time {pseq['wall_s']:.2f} s; batched ...")
+    _, pbat = S.run_stream(preqs, plans, tol, max_iters, arena, use_arrivals=True)
+    log(f"serving: Poisson batched {pbat['wall_s']:.2f} s")
+    return {
+        "workload": (f"{n_requests} independent fixed-source lattice solves to residual {tol:g} "
+                     "(4x4/8x8/16x16 cells, 10-50 layers, 1-7 groups, 8-32 azimuthal x 2-6 "
+                     "polar, 0.05/0.2 cm spacing)"),
+        "arena_bytes": arena,
+        "all_converged": conv,
+        "max_rel_diff_batched_vs_alone": err,
+        "offline": {"batched": S.summarize(bat, n_requests),
+                    "one_at_a_time": S.summarize(seq, n_requests),
+                    "throughput_ratio": seq["wall_s"] / bat["wall_s"]},
+        "poisson": {"rate_req_per_s": rate,
+                    "batched": S.summarize(pbat, n_requests),
+                    "one_at_a_time": S.summarize(pseq, n_requests)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +121,9 @@ def main():
     ap.add_argument("--workload", default="lattice8")
     ap.add_argument("--oracle-iters", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=32,
+                    help="requests in the serving comparison (0: skip it)")
+    ap.add_argument("--serving-arena-gib", type=float, default=8.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -104,6 +154,7 @@ def main():
     cpu = None
     parity = None
     if not args.no_cpu_baseline:
+        log("cpu baseline: oracle iterations ...")
         threads = min(16, len(os.sched_getaffinity(0)))
         ophi, cpu = cpu_baseline(prob, args.oracle_iters, threads)
         solver.reset()
@@ -111,6 +162,7 @@ def main():
         gphi = solver.flux()
         parity = float(np.max(np.abs(gphi - ophi) / np.maximum(np.abs(ophi), 1e-300)))
 
+    log("timed iterations ...")
     solver.reset()
     if args.warmup > 0:
         solver.iterate(args.warmup, stats=False)
@@ -125,6 +177,9 @@ def main():
     sweep_s = st["sweep_ms_median"] * 1e-3
     achieved = BYTES_PER_SEG_GROUP * segg / sweep_s / 1e9
     traffic = load_traffic("k_sweep", args.workload)
+    solver.close()
+    serving = serving_bench(args.serving_requests, args.serving_arena_gib) \
+        if args.serving_requests > 0 else None
     line = {
         "metric": "segment-group integrations/s at 1e-5 vs FP64",
         "value": value,
@@ -157,6 +212,7 @@ def main():
             "traffic": traffic,
         },
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
 

@@ -97,6 +97,7 @@ typedef struct {
 
 typedef struct moc_plan moc_plan;
 typedef struct moc_solver moc_solver;
+typedef struct moc_server moc_server;
 
 typedef struct {
     long long n_fsr, n_regions;
@@ -216,6 +217,42 @@ MOC_API int moc_sweep_items(moc_solver *s, long long n_items, const long long *i
  * only cap are written). */
 MOC_API int moc_trace_tracks(moc_solver *s, long long n, const long long *track_ids, int cap,
                              int *fsr_out, double *len_out, int *count_out);
+
+/* ---------------------------------------------------------------- serving */
+
+/* Continuous batching of independent fixed-source solves on one GPU (the
+ * paper's track-level parallelism, section 4.1, applied across requests).
+ * The caller passes a device arena (256-byte aligned, caller-owned, kept
+ * alive until destroy); the server carves its tables from the front and
+ * sub-allocates one workspace per admitted request from the rest (first
+ * fit).  At most max_slots requests run at once.  stream: a non-default
+ * stream enables HIP-graph capture of the batched step (NULL: plain
+ * launches).  Calls from one thread at a time. */
+MOC_API int moc_server_create(void *dev_arena, size_t arena_bytes, int max_slots, void *stream,
+                              moc_server **out);
+MOC_API void moc_server_destroy(moc_server *srv);   /* NULL-safe; waits for the stream */
+/* Bytes of the arena the server keeps for its own tables (host-only query):
+ * a request fits when its workspace_bytes fits in the rest. */
+MOC_API int moc_server_arena_overhead(int max_slots, size_t *bytes);
+
+/* Queue a request (FP32 sweep, stable exponential; opts->sweep_fp64 and
+ * opts->exp_mode must be 0).  The plan and q [n_fsr][G] are copied.
+ * ENOMEM if the request could never fit the arena. */
+MOC_API int moc_server_submit(moc_server *srv, const moc_plan *plan, const double *q,
+                              const moc_solve_opts *opts, unsigned long long *ticket);
+
+/* One step: admit waiting requests in arrival order while a slot is free
+ * and the workspace fits (a request may be overtaken by smaller ones at most
+ * 8 times), run one source iteration of every active request in one batched
+ * launch sequence, and retire requests whose residual < tol or that reached
+ * max_iters.  *n_active / *n_queued (optional) report the state afterwards. */
+MOC_API int moc_server_step(moc_server *srv, int *n_active, int *n_queued);
+
+/* MOC_EBUSY while the request is queued or running.  Once it has retired:
+ * copies its stats and (if flux_out) its flux [n_fsr][G], releases it and
+ * returns MOC_OK (converged) or MOC_ENOTCONV (stopped at max_iters). */
+MOC_API int moc_server_poll(moc_server *srv, unsigned long long ticket, moc_stats *stats,
+                            double *flux_out, size_t n);
 
 MOC_API const char *moc_last_error(void);
 

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmoc.so")
-SOURCES = ["plan.cpp", "sweep.hip", "api.cpp"]
+SOURCES = ["plan.cpp", "sweep.hip", "api.cpp", "server.cpp"]
 ARCH = os.environ.get("MOC_OFFLOAD_ARCH", "gfx950")
 
 

@@ -144,28 +144,7 @@ int moc_solver_create(const moc_plan *plan, void *dev_workspace, size_t ws_bytes
     const moc::Plan &p = plan->p;
     moc_solver *sv = new (std::nothrow) moc_solver();
     if (!sv) return fail(MOC_ENOMEM, "host allocation failed");
-    moc::Solver &s = sv->s;
-    s.info = p.info();
-    s.lay = moc::make_layout(p, ws_bytes >= s.info.workspace_bytes_fp64);
-    if (ws_bytes < s.lay.total) {
-        delete sv;
-        return fail(MOC_ENOMEM, "workspace smaller than moc_plan_info.workspace_bytes");
-    }
-    if ((reinterpret_cast<uintptr_t>(dev_workspace) & 255) != 0) {
-        delete sv;
-        return fail(MOC_EINVAL, "workspace must be 256-byte aligned");
-    }
-    s.ws = static_cast<char *>(dev_workspace);
-    s.stream = static_cast<hipStream_t>(stream);
-    s.P = p.P;
-    s.K = p.K;
-    s.H = p.H;
-    s.h = p.h;
-    std::memcpy(s.bc, p.bc, sizeof(s.bc));
-    int rc = s.upload(p);
-    if (!rc) rc = moc::fill_zero(s.ws + s.lay.off_q, (size_t)p.n_fsr * p.G * 8, s.stream);
-    if (!rc) rc = s.compute_volumes();
-    if (!rc) rc = s.reset();
+    int rc = sv->s.init(p, static_cast<char *>(dev_workspace), ws_bytes, static_cast<hipStream_t>(stream));
     if (rc) {
         delete sv;
         return rc;

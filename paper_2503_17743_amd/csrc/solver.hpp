@@ -12,6 +12,22 @@ namespace moc {
 
 struct SweepArgs;
 struct FsrArgs;
+struct WinArgs;
+
+// One batched source iteration of several problems (serving): device tables
+// of per-problem descriptors and the work list of all their units.
+struct BatchStep {
+    const WinArgs *win_table;   // [n_slots]
+    const FsrArgs *fsr_table;   // [n_slots]
+    const int *blk_pre;         // [n_slots+1] 256-thread blocks per problem (prefix)
+    const int *u_slot, *u_code; // [n_units]
+    double *res_dev;            // [n_slots] residual of each problem
+    int n_slots, n_units, fsr_blocks;
+    size_t lds;                 // dynamic LDS of the batched sweep (max over problems)
+};
+int launch_batch_step(const BatchStep &b, hipStream_t st);
+// 2D segments per LDS window of the windowed sweep (0: does not fit)
+int window_fit(const Plan &p, bool fp64);
 
 void set_error(const std::string &e);
 const char *last_error();
@@ -31,8 +47,12 @@ struct Solver {
     std::vector<hipEvent_t> events;
     int sw32 = 0, sw64 = 0;          // windowed sweep: 2D segments per window (0: direct path)
     std::vector<long long> chunk_off, trk_off;
+    std::vector<int> work_host;      // windowed-sweep work list (longest first)
+    std::vector<float> work_cost;    // estimated cost of each work-list unit
     std::vector<int> cnt;
 
+    // bind to a workspace: layout, upload, volumes, reset (returns moc_status)
+    int init(const Plan &p, char *workspace, size_t ws_bytes, hipStream_t st);
     SweepArgs sweep_args(int fp64, int exp_mode) const;
     FsrArgs fsr_args() const;
     int upload(const Plan &p);
@@ -40,6 +60,8 @@ struct Solver {
     void launch_sweep(SweepArgs a, bool fp64, const int *units = nullptr, int n_units = 0,
                       const int *filt_n = nullptr, const long long *filt_i0 = nullptr);
     int window_size(bool fp64) const { return fp64 ? sw64 : sw32; }
+    WinArgs win_args_for_next_iteration() const;
+    size_t win_lds() const;
     int reset();
     int iterate(int nit, const moc_solve_opts &o, bool time_sweep);
     int read_stats(moc_stats *st);

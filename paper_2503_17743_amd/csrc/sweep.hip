@@ -24,6 +24,7 @@
 #include <string>
 #include <vector>
 
+#include "args.hpp"
 #include "plan.hpp"
 #include "solver.hpp"
 
@@ -117,33 +118,6 @@ __device__ inline int seg_search(const double *__restrict__ pos, int lo, int hi,
     return lo;
 }
 
-struct SweepArgs {
-    const double *cot, *secl, *seca, *wgt;       // [A2][P]
-    const double *t_len;                          // [n2d]
-    const int *t_first, *t_meta, *t_link;         // [n2d+1], [n2d], [2*n2d]
-    const double *seg_pos;                        // [nseg]
-    const int *seg_reg, *reg_mat;                 // [nseg], [n_regions]
-    const double *zeta;                           // [n_stacks]
-    const long long *ilo;                         // [n_stacks]
-    const int *cnt;                               // [n_stacks]
-    const long long *trk_off, *chunk_off;         // [n_stacks+1]
-    const void *sigt;                             // [M][G] float or double
-    const void *qhat;                             // [n_fsr][G] float or double
-    double *acc;                                  // [n_fsr][G]
-    void *psi_in;                                 // boundary buffer read this sweep
-    void *psi_out;                                // boundary buffer written (may be null)
-    const double *psi_entry;                      // per (item, lane) incoming flux (test hook)
-    double *psi_exit;                             // per (item, lane) outgoing flux (test hook)
-    const long long *items;                       // explicit work list or null
-    long long n_items;
-    long long n_stacks;
-    double *scal;
-    double H, h, inv_h, dz;
-    int G, P, K, T;
-    int bc[6];
-    int exp_mode;
-    int mode;                                     // 0 sweep, 1 volume tally
-};
 
 // z of line i of stack s at the start of its 2D track (Eq. 5)
 __device__ inline double line_base(const SweepArgs &a, long long s, long long i) {
@@ -407,20 +381,14 @@ __host__ __device__ inline size_t win_lds_bytes(int Sw, int K, int G, int rbytes
            (size_t)Sw * G * rbytes + (size_t)Sw * 4 + 16;
 }
 
-struct WinArgs {
-    SweepArgs s;
-    const int *work;          // work unit codes 2*t + dir (longest first)
-    const int *filt_n;        // test hook: only this polar stack per unit (or null)
-    const long long *filt_i0; // test hook: only lines [i0, i0+T) of it
-    int Sw;                   // 2D segments per window
-};
 
 __device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // MODE 0: transport sweep; MODE 1: volume tally (W l / 4 pi per FSR).
 // EXPM 0: stable 1 - e^-tau; EXPM 1: 1 - hardware exp (precision study).
 template <typename R, typename B, int MODE, int EXPM, bool BWD>
-__device__ __forceinline__ void sweep_unit(const WinArgs &wa, unsigned char *smem) {
+__device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit,
+                                           unsigned char *smem) {
     const SweepArgs &a = wa.s;
     const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6);
     const int G = a.G, K = a.K, P = a.P, T = a.T;
@@ -437,8 +405,6 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, unsigned char *sme
     R *s_st = q_l + (size_t)Sw * KG;
     int *s_reg = (int *)(s_st + (size_t)Sw * G);
 
-    const int unit = blockIdx.x;
-    const int code = wa.work[unit];
     const long long t = code >> 1;
     constexpr int dir = BWD ? 1 : 0;
     const int meta = a.t_meta[t];
@@ -653,8 +619,26 @@ template <typename R, typename B, int MODE, int EXPM>
 __global__ __launch_bounds__(kWinThreads) void k_sweep_win(WinArgs wa) {
     extern __shared__ __align__(16) unsigned char smem[];
     // the direction is uniform per workgroup: specialise the whole unit on it
-    if (wa.work[blockIdx.x] & 1) sweep_unit<R, B, MODE, EXPM, true>(wa, smem);
-    else sweep_unit<R, B, MODE, EXPM, false>(wa, smem);
+    const int code = wa.work[blockIdx.x];
+    if (code & 1) sweep_unit<R, B, MODE, EXPM, true>(wa, code, blockIdx.x, smem);
+    else sweep_unit<R, B, MODE, EXPM, false>(wa, code, blockIdx.x, smem);
+}
+
+// Batched form for serving: work unit u belongs to problem slot u_slot[u] and
+// is (2D track, direction) u_code[u] of that problem; every problem brings its
+// own descriptor (pointers into its own workspace, sizes, window length), so
+// the units of all active problems run in one launch.
+__global__ __launch_bounds__(kWinThreads) void k_sweep_win_multi(const WinArgs *__restrict__ descs,
+                                                                  const int *__restrict__ u_slot,
+                                                                  const int *__restrict__ u_code) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int slot = u_slot[blockIdx.x];
+    const int code = u_code[blockIdx.x];
+    // descriptors are never written during the launch (restrict): their
+    // fields load once instead of after every store to the tallies
+    const WinArgs &wa = descs[slot];
+    if (code & 1) sweep_unit<float, float, 0, 0, true>(wa, code, blockIdx.x, smem);
+    else sweep_unit<float, float, 0, 0, false>(wa, code, blockIdx.x, smem);
 }
 
 // ------------------------------------------------------------------ trace hook
@@ -707,19 +691,9 @@ __global__ void k_trace(SweepArgs a, const long long *tracks, long long ntr, int
 
 // ------------------------------------------------------------------ source / finalize
 
-struct FsrArgs {
-    const double *q, *sigt, *sigs, *vol;
-    const int *reg_mat;
-    double *phi, *acc, *qhat64;
-    float *qhat32;
-    double *scal;
-    long long n;        // n_fsr * G
-    int G, K;
-};
 
 // qhat = (sum_g' Sigma_s[g'->g] phi_g' + Q_g) / (4 pi Sigma_t,g); clears the tally.
-__global__ __launch_bounds__(256) void k_source(FsrArgs a) {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline void source_elem(const FsrArgs &a, long long i) {
     if (i >= a.n) return;
     const int G = a.G;
     const long long j = i / G;
@@ -736,8 +710,7 @@ __global__ __launch_bounds__(256) void k_source(FsrArgs a) {
 }
 
 // phi = 4 pi qhat + acc / (Sigma_t V) (Eq. 4 estimator); residual and totals.
-__global__ __launch_bounds__(256) void k_finalize(FsrArgs a) {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline void finalize_elem(const FsrArgs &a, long long i, int slot_seed) {
     double res = 0.0, bal = 0.0, absb = 0.0, src = 0.0;
     if (i < a.n) {
         const int G = a.G;
@@ -764,12 +737,60 @@ __global__ __launch_bounds__(256) void k_finalize(FsrArgs a) {
     absb = wave_sum(absb);
     src = wave_sum(src);
     if ((threadIdx.x & 63) == 0) {
-        const int sl = (int)(((long long)blockIdx.x * 4 + (threadIdx.x >> 6)) % kSlots);
+        const int sl = (int)(((long long)slot_seed * 4 + (threadIdx.x >> 6)) % kSlots);
         atomicMax((unsigned long long *)&a.scal[0], (unsigned long long)__double_as_longlong(res));
         unsafeAtomicAdd(&a.scal[slot_index(Q_BAL, sl)], bal);
         unsafeAtomicAdd(&a.scal[slot_index(Q_ABS, sl)], absb);
         unsafeAtomicAdd(&a.scal[slot_index(Q_SRC, sl)], src);
     }
+}
+
+__global__ __launch_bounds__(256) void k_source(FsrArgs a) {
+    source_elem(a, (long long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_finalize(FsrArgs a) {
+    finalize_elem(a, (long long)blockIdx.x * blockDim.x + threadIdx.x, blockIdx.x);
+}
+
+// Batched forms: problem slot of a block from the block prefix blk_pre
+// (n_slots + 1 entries); the block index inside the problem follows.
+__device__ inline int slot_of_block(const int *blk_pre, int n_slots, int b) {
+    int lo = 0, hi = n_slots;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (blk_pre[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_source_multi(const FsrArgs *__restrict__ args,
+                                                      const int *__restrict__ blk_pre,
+                                                      int n_slots) {
+    const int sl = slot_of_block(blk_pre, n_slots, blockIdx.x);
+    source_elem(args[sl], (long long)(blockIdx.x - blk_pre[sl]) * blockDim.x + threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_finalize_multi(const FsrArgs *__restrict__ args,
+                                                        const int *__restrict__ blk_pre,
+                                                        int n_slots) {
+    const int sl = slot_of_block(blk_pre, n_slots, blockIdx.x);
+    const int b = blockIdx.x - blk_pre[sl];
+    finalize_elem(args[sl], (long long)b * blockDim.x + threadIdx.x, b);
+}
+
+// Clear the scalar block of every active problem (blockIdx.y = slot).
+__global__ void k_clear_scal_multi(const FsrArgs *args, int words) {
+    unsigned *p = (unsigned *)args[blockIdx.y].scal;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < words; i += gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+// Residual of every active problem into one compact array.
+__global__ void k_gather_residual(const FsrArgs *args, int n_slots, double *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_slots) out[i] = args[i].scal[0];
 }
 
 __global__ void k_fill_u32(unsigned *p, unsigned v, size_t n) {
@@ -907,17 +928,8 @@ int Solver::upload(const Plan &p) {
     // windowed sweep: window size from the LDS budget, and the work list of
     // (2D track, direction) units ordered by decreasing work (lines x 2D
     // segments), so the longest units start first
-    int max_seg = 1;
-    for (int64_t t = 0; t < p.n2d; ++t)
-        max_seg = std::max<int>(max_seg, (int)(p.seg_first[t + 1] - p.seg_first[t]));
-    auto fit = [&](int rbytes) {
-        int sw = 0;
-        while (sw < max_seg && win_lds_bytes(sw + 1, p.K, p.G, rbytes) <= kWinLdsBudget) ++sw;
-        return sw;
-    };
-    sw32 = fit(4);
-    sw64 = fit(8);
-    if (p.P > kMaxPolar) sw32 = sw64 = 0;
+    sw32 = window_fit(p, false);
+    sw64 = window_fit(p, true);
     std::vector<std::pair<double, int>> est(p.n2d);
     for (int64_t t = 0; t < p.n2d; ++t) {
         double lines = 0;
@@ -929,11 +941,15 @@ int Solver::upload(const Plan &p) {
         return x.first > y.first;
     });
     std::vector<int> work(2 * p.n2d);
+    work_cost.resize(2 * p.n2d);
     for (int64_t i = 0; i < p.n2d; ++i) {
         work[2 * i] = 2 * est[i].second;
         work[2 * i + 1] = 2 * est[i].second + 1;
+        // in wave passes: a wave carries T lines of all groups
+        work_cost[2 * i] = work_cost[2 * i + 1] = (float)(est[i].first / p.T);
     }
     HIPCHK(put(lay.off_work, work.data(), work.size() * 4));
+    work_host = work;
     chunk_off.assign(p.chunk_off.begin(), p.chunk_off.end());
     trk_off.assign(p.trk_off.begin(), p.trk_off.end());
     cnt.assign(p.cnt.begin(), p.cnt.end());
@@ -999,6 +1015,67 @@ void Solver::launch_sweep(SweepArgs a, bool fp64, const int *units, int n_units,
         if (fp64) k_sweep<double, float><<<grid, 256, 0, stream>>>(a);
         else k_sweep<float, float><<<grid, 256, 0, stream>>>(a);
     }
+}
+
+int window_fit(const Plan &p, bool fp64) {
+    if (p.P > kMaxPolar) return 0;
+    int max_seg = 1;
+    for (int64_t t = 0; t < p.n2d; ++t)
+        max_seg = std::max<int>(max_seg, (int)(p.seg_first[t + 1] - p.seg_first[t]));
+    int sw = 0;
+    while (sw < max_seg && win_lds_bytes(sw + 1, p.K, p.G, fp64 ? 8 : 4) <= kWinLdsBudget) ++sw;
+    return sw;
+}
+
+int Solver::init(const Plan &p, char *workspace, size_t ws_bytes, hipStream_t st) {
+    info = p.info();
+    lay = make_layout(p, ws_bytes >= info.workspace_bytes_fp64);
+    if (ws_bytes < lay.total) {
+        set_error("workspace smaller than moc_plan_info.workspace_bytes");
+        return MOC_ENOMEM;
+    }
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) {
+        set_error("workspace must be 256-byte aligned");
+        return MOC_EINVAL;
+    }
+    ws = workspace;
+    stream = st;
+    P = p.P;
+    K = p.K;
+    H = p.H;
+    h = p.h;
+    std::memcpy(bc, p.bc, sizeof(bc));
+    int rc = upload(p);
+    if (!rc) rc = fill_zero(ws + lay.off_q, (size_t)p.n_fsr * p.G * 8, stream);
+    if (!rc) rc = compute_volumes();
+    if (!rc) rc = reset();
+    return rc;
+}
+
+WinArgs Solver::win_args_for_next_iteration() const {
+    WinArgs wa;
+    std::memset(&wa, 0, sizeof(wa));
+    wa.s = sweep_args(0, 0);
+    const bool odd = ((iter + 1) % 2) == 1;
+    wa.s.psi_in = ws + (odd ? lay.off_psi0 : lay.off_psi1);
+    wa.s.psi_out = ws + (odd ? lay.off_psi1 : lay.off_psi0);
+    wa.work = ws_ptr<int>(ws, lay.off_work);
+    wa.Sw = sw32;
+    return wa;
+}
+
+size_t Solver::win_lds() const { return win_lds_bytes(sw32, K, info.n_groups, 4); }
+
+int launch_batch_step(const BatchStep &b, hipStream_t st) {
+    if (b.n_slots <= 0) return MOC_OK;
+    k_clear_scal_multi<<<dim3(8, b.n_slots), 256, 0, st>>>(b.fsr_table, 128 * 1024 / 4);
+    k_source_multi<<<b.fsr_blocks, 256, 0, st>>>(b.fsr_table, b.blk_pre, b.n_slots);
+    if (b.n_units > 0)
+        k_sweep_win_multi<<<b.n_units, kWinThreads, b.lds, st>>>(b.win_table, b.u_slot, b.u_code);
+    k_finalize_multi<<<b.fsr_blocks, 256, 0, st>>>(b.fsr_table, b.blk_pre, b.n_slots);
+    k_gather_residual<<<(b.n_slots + 255) / 256, 256, 0, st>>>(b.fsr_table, b.n_slots, b.res_dev);
+    HIPCHK(hipGetLastError());
+    return MOC_OK;
 }
 
 int Solver::reset() {

@@ -100,6 +100,12 @@ def lib():
         "moc_flux_device_ptr": ([VP, C.POINTER(VP)], C.c_int),
         "moc_sweep_items": ([VP, C.c_longlong, VP, VP, VP, C.c_int, VP, VP], C.c_int),
         "moc_trace_tracks": ([VP, C.c_longlong, VP, C.c_int, VP, VP, VP], C.c_int),
+        "moc_server_create": ([VP, C.c_size_t, C.c_int, VP, C.POINTER(VP)], C.c_int),
+        "moc_server_destroy": ([VP], None),
+        "moc_server_arena_overhead": ([C.c_int, C.POINTER(C.c_size_t)], C.c_int),
+        "moc_server_submit": ([VP, VP, VP, C.POINTER(SolveOpts), C.POINTER(C.c_ulonglong)], C.c_int),
+        "moc_server_step": ([VP, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
+        "moc_server_poll": ([VP, C.c_ulonglong, C.POINTER(Stats), VP, C.c_size_t], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -278,6 +284,69 @@ class Solver:
         _check(lib().moc_trace_tracks(self._h, len(ids), _p(ids), int(cap), _p(fsr), _p(ln), _p(cnt)))
         return [(fsr[i, :min(cnt[i], cap)].copy(), ln[i, :min(cnt[i], cap)].copy(), int(cnt[i]))
                 for i in range(len(ids))]
+
+
+class Server:
+    """Continuous-batching server on a device arena (torch uint8 tensor) and
+    its own non-default stream (so the batched step can be graph-captured)."""
+
+    def __init__(self, arena_bytes, max_slots=64, device="cuda"):
+        import torch
+        self.device = torch.device(device)
+        self.stream = torch.cuda.Stream(self.device)
+        self.arena = torch.empty(int(arena_bytes) + 256, dtype=torch.uint8, device=self.device)
+        torch.cuda.synchronize(self.device)
+        base = self.arena.data_ptr()
+        aligned = (base + 255) & ~255
+        h = VP()
+        _check(lib().moc_server_create(VP(aligned), self.arena.numel() - (aligned - base),
+                                       int(max_slots), VP(self.stream.cuda_stream), C.byref(h)))
+        self._h = h
+        self._shape = {}
+
+    @staticmethod
+    def overhead_bytes(max_slots=64) -> int:
+        b = C.c_size_t()
+        _check(lib().moc_server_arena_overhead(int(max_slots), C.byref(b)))
+        return b.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().moc_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, plan: Plan, q, tol=1e-6, max_iters=1000) -> int:
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        o = SolveOpts(float(tol), int(max_iters), 0, 0)
+        t = C.c_ulonglong()
+        _check(lib().moc_server_submit(self._h, plan._h, _p(q), C.byref(o), C.byref(t)))
+        self._shape[t.value] = (plan.info["n_fsr"], plan.info["n_groups"])
+        return t.value
+
+    def step(self):
+        na, nq = C.c_int(), C.c_int()
+        _check(lib().moc_server_step(self._h, C.byref(na), C.byref(nq)))
+        return na.value, nq.value
+
+    def poll(self, ticket):
+        """None while queued or running; else (flux, stats) and the request is released."""
+        shape = self._shape[ticket]
+        flux = np.zeros(shape)
+        st = Stats()
+        rc = lib().moc_server_poll(self._h, C.c_ulonglong(ticket), C.byref(st), _p(flux), flux.size)
+        if rc == MOC_EBUSY:
+            return None
+        _check(rc, allow=(MOC_ENOTCONV,))
+        del self._shape[ticket]
+        d = st.as_dict()
+        d["converged"] = rc == MOC_OK
+        return flux, d
 
 
 def solve(prob, tol=None, max_iters=None, sweep_fp64=False, exp_mode=0):

@@ -245,12 +245,12 @@ class Request:
 
 def serving_stream(n_requests=512, seed=4, rate_per_s=None, sizes=(4, 8, 16),
                    layers=(10, 50), groups=(1, 7), azim=(8, 32), polar=(2, 4, 6),
-                   radial=0.05, axial=0.2) -> List[Request]:
-    """Independent fixed-source lattice problems of random size with Poisson
-    arrival times (exponential gaps of mean 1/rate; rate None = all at t=0)."""
+                   radial=0.05, axial=0.2, tol=1e-6) -> List[Request]:
+    """Independent fixed-source lattice problems of random size (the problems
+    depend only on seed) with Poisson arrival times (exponential gaps of mean
+    1/rate from a generator of their own; rate None = all at t=0)."""
     rng = np.random.default_rng(seed)
-    out = []
-    t = 0.0
+    probs = []
     for i in range(n_requests):
         n = int(rng.choice(sizes))
         k = int(rng.integers(layers[0], layers[1] + 1))
@@ -258,12 +258,17 @@ def serving_stream(n_requests=512, seed=4, rate_per_s=None, sizes=(4, 8, 16),
         a = int(rng.choice(np.arange(azim[0], azim[1] + 1, 4)))
         pp = int(rng.choice(polar))
         sub_seed = int(rng.integers(0, 2**31 - 1))
-        prob = _lattice(f"req{i}", sub_seed, n, float(k), k, 2, g, a, pp, radial, axial,
-                        tol=1e-8, max_iters=1000)
-        if rate_per_s:
-            t += rng.exponential(1.0 / rate_per_s)
-        out.append(Request(prob, t))
-    return out
+        probs.append(_lattice(f"req{i}", sub_seed, n, float(k), k, 2, g, a, pp, radial, axial,
+                              tol=tol, max_iters=1000))
+    return with_arrivals(probs, rate_per_s, seed)
+
+
+def with_arrivals(problems, rate_per_s, seed=4) -> List[Request]:
+    """Poisson arrivals for a list of problems (rate None: all at t=0)."""
+    if not rate_per_s:
+        return [Request(p, 0.0) for p in problems]
+    gaps = np.random.default_rng([seed, 1]).exponential(1.0 / rate_per_s, len(problems))
+    return [Request(p, float(t)) for p, t in zip(problems, np.cumsum(gaps))]
 
 
 CONFIGS = {

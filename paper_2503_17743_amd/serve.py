@@ -1,0 +1,100 @@
+"""Serving driver: a stream of independent fixed-source requests, run through
+the continuous-batching server and, for comparison, one at a time in arrival
+order on the same GPU.  Latency of a request = its completion time minus its
+arrival time; throughput = requests (and segment-group updates) per second of
+wall time."""
+from __future__ import annotations
+
+import time
+from typing import Dict, List
+
+import numpy as np
+
+from . import moc, problems as P
+
+
+def plan_requests(reqs: List[P.Request]):
+    return [moc.Plan(r.problem) for r in reqs]
+
+
+def _arrivals(reqs, use_arrivals):
+    return np.array([r.arrival_s for r in reqs]) if use_arrivals else np.zeros(len(reqs))
+
+
+def one_at_a_time(reqs, plans, tol, max_iters, use_arrivals=False):
+    """FIFO, one request on the GPU at a time: wait for its arrival, bind a
+    solver, solve to tol, read the flux back, release the workspace."""
+    import torch
+    arr = _arrivals(reqs, use_arrivals)
+    out, stats = [], []
+    lat = np.zeros(len(reqs))
+    segg = 0
+    t0 = time.perf_counter()
+    for i, (r, pl) in enumerate(zip(reqs, plans)):
+        wait = arr[i] - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        s = moc.Solver(pl, fp64_boundary=False)
+        s.set_source(r.problem.q)
+        phi, st = s.solve(tol=tol, max_iters=max_iters)
+        s.close()
+        del s
+        lat[i] = time.perf_counter() - t0 - arr[i]
+        segg += st["seg_group_updates"] * st["iters"]
+        out.append(phi)
+        stats.append(st)
+    torch.cuda.synchronize()
+    return out, {"wall_s": time.perf_counter() - t0, "seg_group_updates": segg,
+                 "latency_s": lat.tolist(), "stats": stats}
+
+
+def run_stream(reqs, plans, tol, max_iters, arena_bytes, max_slots=64, use_arrivals=False):
+    """Submit each request at its arrival time (all at t=0 unless use_arrivals)
+    and step the server until every request is done."""
+    srv = moc.Server(arena_bytes, max_slots=max_slots)
+    n = len(reqs)
+    arr = _arrivals(reqs, use_arrivals)
+    tickets: Dict[int, int] = {}
+    done: Dict[int, tuple] = {}
+    lat = np.zeros(n)
+    segg = 0
+    steps = 0
+    max_active = 0
+    t0 = time.perf_counter()
+    nxt = 0
+    while len(done) < n:
+        now = time.perf_counter() - t0
+        while nxt < n and arr[nxt] <= now:
+            tickets[srv.submit(plans[nxt], reqs[nxt].problem.q, tol, max_iters)] = nxt
+            nxt += 1
+        if not tickets:
+            time.sleep(max(0.0, min(arr[nxt] - now, 0.01)))
+            continue
+        na, _ = srv.step()
+        steps += 1
+        max_active = max(max_active, na)
+        now = time.perf_counter() - t0
+        for tk in list(tickets):
+            res = srv.poll(tk)
+            if res is None:
+                continue
+            i = tickets.pop(tk)
+            done[i] = res
+            lat[i] = now - arr[i]
+            segg += res[1]["seg_group_updates"] * res[1]["iters"]
+    wall = time.perf_counter() - t0
+    srv.close()
+    return [done[i][0] for i in range(n)], {
+        "wall_s": wall, "seg_group_updates": segg, "latency_s": lat.tolist(), "steps": steps,
+        "max_active": max_active, "stats": [done[i][1] for i in range(n)]}
+
+
+def summarize(d, n):
+    lat = np.array(d["latency_s"])
+    out = {"requests": n, "wall_s": d["wall_s"], "req_per_s": n / d["wall_s"],
+           "seg_group_per_s": d["seg_group_updates"] / d["wall_s"],
+           "latency_p50_s": float(np.percentile(lat, 50)),
+           "latency_p99_s": float(np.percentile(lat, 99))}
+    if "max_active" in d:
+        out["max_active"] = d["max_active"]
+    return out
