@@ -98,3 +98,34 @@ def summarize(d, n):
     if "max_active" in d:
         out["max_active"] = d["max_active"]
     return out
+
+
+def main(argv=None):
+    """Run a seeded request stream one way and print one JSON summary line:
+    python -m paper_2503_17743_amd.serve [--requests N] [--mode batched|one]"""
+    import argparse
+    import json
+    import torch
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--requests", type=int, default=32)
+    ap.add_argument("--mode", choices=("batched", "one"), default="batched")
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--max-iters", type=int, default=400)
+    ap.add_argument("--arena-gib", type=float, default=8.0)
+    ap.add_argument("--rate", type=float, default=0.0, help="Poisson arrivals per s (0: all at t=0)")
+    args = ap.parse_args(argv)
+    torch.cuda.set_device(0)
+    probs = [r.problem for r in P.serving_stream(n_requests=args.requests)]
+    reqs = P.with_arrivals(probs, args.rate or None)
+    plans = plan_requests(reqs)
+    arrivals = args.rate > 0
+    if args.mode == "one":
+        _, d = one_at_a_time(reqs, plans, args.tol, args.max_iters, use_arrivals=arrivals)
+    else:
+        arena = moc.Server.overhead_bytes(64) + int(args.arena_gib * (1 << 30))
+        _, d = run_stream(reqs, plans, args.tol, args.max_iters, arena, use_arrivals=arrivals)
+    print(json.dumps({"mode": args.mode, **summarize(d, args.requests)}), flush=True)
+
+
+if __name__ == "__main__":
+    main()
