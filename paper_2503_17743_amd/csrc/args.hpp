@@ -27,6 +27,7 @@ struct SweepArgs {
     double *scal;
     double H, h, inv_h, dz;
     int G, P, K, T;
+    int C, GL;                                    // group chunks across lanes, groups per lane
     int bc[6];
     int exp_mode;
     int mode;                                     // 0 sweep, 1 volume tally

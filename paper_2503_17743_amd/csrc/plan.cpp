@@ -465,7 +465,7 @@ std::string Plan::build(const moc_geometry &g, const moc_tracking &t, const moc_
             cnt[s] = hi >= lo ? hi - lo + 1 : 0;
         }
     }
-    T = std::max(1, 64 / G);
+    T = 64 / group_chunks(G);
     trk_off.assign(n_stacks + 1, 0);
     chunk_off.assign(n_stacks + 1, 0);
     for (int64_t s = 0; s < n_stacks; ++s) {
@@ -540,10 +540,10 @@ Layout make_layout(const Plan &p, bool psi64) {
     l.psi_bytes = 2 * ((psi + 255) & ~size_t(255));
     l.off_work = take((size_t)2 * p.n2d * 4);
     l.off_scal = take(128 * 1024);
-    l.n_item_cap = 4096;
+    l.n_item_cap = 512;
     l.off_items = take(l.n_item_cap * 8);
-    l.off_psi_entry = take(l.n_item_cap * 64 * 8);
-    l.off_psi_exitb = take(l.n_item_cap * 64 * 8);
+    l.off_psi_entry = take(l.n_item_cap * kItemStride * 8);
+    l.off_psi_exitb = take(l.n_item_cap * kItemStride * 8);
     l.off_units = take(l.n_item_cap * 4);
     l.off_filt_n = take(l.n_item_cap * 4);
     l.off_filt_i0 = take(l.n_item_cap * 8);

@@ -21,6 +21,15 @@ constexpr double kTrackEps = 1e-9;
 // carry the rounding noise of the chain phase (up to ~1e-11 cm on long
 // cycles), far below this; genuine pieces this short are vanishingly rare.
 constexpr double kMinSeg = 1e-9;
+// Sweep lane layout: the G groups are split into C = ceil(G / kGL) chunks
+// across lanes; a lane holds the flux of up to kGL groups in registers and a
+// wave bundle covers T = 64 / C lines.
+constexpr int kGL = 8;
+inline int group_chunks(int G) { return (G + kGL - 1) / kGL; }
+inline int groups_per_lane(int G) { return (G + group_chunks(G) - 1) / group_chunks(G); }
+// Per-item stride (doubles) of the test hooks' entry/exit flux buffers: T * G
+// never exceeds 64 * kGL.
+constexpr int kItemStride = 64 * kGL;
 
 struct Plan {
     // ---- problem ----

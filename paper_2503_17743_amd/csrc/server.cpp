@@ -206,12 +206,20 @@ int Server::rebuild() {
         const std::vector<float> &c = active[i]->solver.work_cost;
         return c.empty() ? 0.f : c[0];
     };
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return head(x) > head(y); });
+    // problems whose groups fit one lane (G <= 8) first: they run in their
+    // own launch with the one-chunk lane layout
+    auto one_chunk = [&](int i) { return active[i]->solver.info.n_groups <= kGL; };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        if (one_chunk(x) != one_chunk(y)) return one_chunk(x);
+        return head(x) > head(y);
+    });
     std::vector<int> us2, uc2;
+    int n_c1 = 0;
     for (int i : order) {
         const std::vector<int> &w = active[i]->solver.work_host;
         us2.insert(us2.end(), w.size(), i);
         uc2.insert(uc2.end(), w.begin(), w.end());
+        if (one_chunk(i)) n_c1 += (int)w.size();
     }
     if (!us2.empty()) {
         SRV_HIPCHK(hipMemcpyAsync(d_uslot, us2.data(), us2.size() * 4, hipMemcpyHostToDevice, stream));
@@ -228,6 +236,7 @@ int Server::rebuild() {
     batch.res_dev = d_res;
     batch.n_slots = n;
     batch.n_units = (int)us2.size();
+    batch.n_units_c1 = n_c1;
     batch.fsr_blocks = blk[n];
     batch.lds = lds;
     if (exec) {

@@ -23,6 +23,7 @@ struct BatchStep {
     const int *u_slot, *u_code; // [n_units]
     double *res_dev;            // [n_slots] residual of each problem
     int n_slots, n_units, fsr_blocks;
+    int n_units_c1;             // units [0, n_units_c1) belong to problems with G <= 8
     size_t lds;                 // dynamic LDS of the batched sweep (max over problems)
 };
 int launch_batch_step(const BatchStep &b, hipStream_t st);

@@ -3,16 +3,20 @@
 //   tally + boundary angular-flux exchange -> finalize (Eq. 4 estimator,
 //   residual, balance).
 //
-// Sweep mapping.  One wavefront (64 lanes) takes a bundle of T = 64/G
-// consecutive lines of one z-stack (paper Eq. 5: same 2D track, same polar
-// angle, dz apart) in one sweep direction; lane = (line in bundle, group).
-// All lines of a bundle project onto the same 2D track, so the wave walks
-// that track's 2D segments in lockstep (uniform loop, the segment record is
-// shared by the whole wave) and every lane splits the current 2D segment at
-// the axial planes it crosses (Eqs. 6-11 evaluated per line: a line inside one
-// layer over the whole 2D segment has length ds/sin(theta) (Eq. 8), a line
-// crossing a whole layer has length dz_layer/|cos(theta)| (Eq. 11)).  3D
-// segments live only in registers: nothing per 3D track or segment is stored.
+// Sweep mapping.  One wavefront (64 lanes) takes a bundle of T consecutive
+// lines of one z-stack (paper Eq. 5: same 2D track, same polar angle, dz
+// apart) in one sweep direction.  Lane = (line in bundle, group chunk): the G
+// groups are split into C = ceil(G/8) chunks across lanes and each lane keeps
+// the angular flux of its chunk's (at most 8) groups in registers, so T =
+// 64/C lines (64 for G <= 8).  All lines of a bundle project onto the same 2D
+// track, so the wave walks that track's 2D segments in lockstep (uniform loop,
+// the segment record is shared by the whole wave) and every lane splits the
+// current 2D segment at the axial planes its line crosses (Eqs. 6-11
+// evaluated per line: a line inside one layer over the whole 2D segment has
+// length ds/sin(theta) (Eq. 8), a line crossing a whole layer has length
+// dz_layer/|cos(theta)| (Eq. 11)); the piece geometry is computed once per
+// line and reused for all groups of the lane.  3D segments live only in
+// registers: nothing per 3D track or segment is stored.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,6 +26,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "args.hpp"
@@ -245,9 +250,9 @@ __device__ inline long long successor_slot(const SweepArgs &a, const Bound &b, l
 
 // ------------------------------------------------------------------ direct sweep
 // One wave = one work item (2*chunk + dir): a bundle of T consecutive lines of
-// one z-stack, lane = (line, group), every 3D segment tallied with one FP64
-// global atomic.  Used when an LDS window of one 2D segment x all layers x
-// all groups does not fit (very large K*G).
+// one z-stack, lane = (line, group chunk), every 3D segment-group tallied with
+// one FP64 global atomic.  Used when an LDS window of one 2D segment x all
+// layers x all groups does not fit (very large K*G).
 template <typename R, typename B>
 __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
     const int lane = threadIdx.x & 63;
@@ -263,7 +268,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
         else hi = mid;
     }
     const long long s = lo;
-    const int P = a.P, G = a.G, K = a.K;
+    const int P = a.P, G = a.G, K = a.K, C = a.C, GL = a.GL;
     const long long t = s / P;
     const int n = (int)(s - t * P);
     const int meta = a.t_meta[t];
@@ -271,10 +276,11 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
     const double c = a.cot[an], secl = a.secl[an], W = a.wgt[an];
     const double Lt = a.t_len[t];
     const int f0 = a.t_first[t], f1 = a.t_first[t + 1];
-    const int tr = lane / G;
-    const int g = lane - tr * G;
+    const int tr = lane / C;
+    const int g0 = (lane - tr * C) * GL;
+    const int ng = max(0, min(GL, G - g0));
     const long long zi = (chunk - a.chunk_off[s]) * a.T + tr;
-    const bool active = (tr < a.T) && (zi < (long long)a.cnt[s]);
+    const bool active = (tr < a.T) && (zi < (long long)a.cnt[s]) && ng > 0;
     const double base = line_base(a, s, zi);
     double ls = 1e300, le = -1e300;
     if (active) clip_line(base, c, Lt, a.H, ls, le);
@@ -282,13 +288,20 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
     const long long slot_in = 2 * (a.trk_off[s] + zi) + dir;
     const R *sigt = (const R *)a.sigt;
     const R *qhat = (const R *)a.qhat;
-    R psi = 0;
+    const size_t hook = (size_t)w * kItemStride + (size_t)tr * G + g0;
+    R psi[kGL];
+#pragma unroll
+    for (int j = 0; j < kGL; ++j) psi[j] = 0;
     double s_in = 0.0;
     if (active && a.mode == 0) {
-        if (a.psi_entry) psi = (R)a.psi_entry[w * 64 + lane];
-        else if (!is_vacuum(a, boundary_of(base, c, Lt, a.H, dir, false, meta)))
-            psi = (R)((const B *)a.psi_in)[slot_in * G + g];
-        s_in = W * (double)psi;
+        const bool from_vacuum = is_vacuum(a, boundary_of(base, c, Lt, a.H, dir, false, meta));
+#pragma unroll
+        for (int j = 0; j < kGL; ++j)
+            if (j < ng) {
+                if (a.psi_entry) psi[j] = (R)a.psi_entry[hook + j];
+                else if (!from_vacuum) psi[j] = (R)((const B *)a.psi_in)[slot_in * G + g0 + j];
+                s_in += W * (double)psi[j];
+            }
     }
     long long nseg = 0;
     const int k_first = seg_search(a.seg_pos, f0, f1, l_lo);
@@ -305,23 +318,26 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
         const double e = dir ? fmax(s0, ls) : fmin(s1, le);
         if (!(dir ? e < wk.lcur : e > wk.lcur)) continue;
         const long long jb = (long long)reg * K;
-        const R st = sigt[a.reg_mat[reg] * G + g];
+        const R *st = sigt + a.reg_mat[reg] * G + g0;
         auto piece = [&](int kz, double l3, bool valid) {
             if (!valid) return;
-            const long long j = jb + kz;
+            const long long j0 = (jb + kz) * G + g0;
             if (a.mode == 1) {
-                if (g == 0) unsafeAtomicAdd(&a.acc[j], W * l3 / kFourPi);
+                if (g0 == 0) unsafeAtomicAdd(&a.acc[jb + kz], W * l3 / kFourPi);
                 return;
             }
-            const R q = qhat[j * G + g];
-            const R d = (psi - q) * one_minus_exp<R>(st * (R)l3, a.exp_mode);   // Eq. 3
-            psi -= d;
-            unsafeAtomicAdd(&a.acc[j * G + g], W * (double)d);
+#pragma unroll
+            for (int j = 0; j < kGL; ++j)
+                if (j < ng) {
+                    const R d = (psi[j] - qhat[j0 + j]) * one_minus_exp<R>(st[j] * (R)l3, a.exp_mode);
+                    psi[j] -= d;                                                   // Eq. 3
+                    unsafeAtomicAdd(&a.acc[j0 + j], W * (double)d);
+                }
         };
         nseg += dir ? walk_segment<true>(wk, e, secl, K, piece) : walk_segment<false>(wk, e, secl, K, piece);
     }
     if (a.mode == 1) {
-        const long long tot = wave_sum_ll(active && g == 0 ? nseg : 0);
+        const long long tot = wave_sum_ll(active && g0 == 0 ? nseg : 0);
         if (lane == 0)
             atomicAdd((unsigned long long *)&a.scal[slot_index(Q_NSEG, (int)(w % kSlots))],
                       (unsigned long long)tot);
@@ -330,22 +346,31 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
     double leak = 0.0, s_out = 0.0;
     long long link_err = 0;
     if (active) {
-        s_out = W * (double)psi;
-        if (a.psi_exit) a.psi_exit[w * 64 + lane] = (double)psi;
+        double wpsi = 0.0;
+#pragma unroll
+        for (int j = 0; j < kGL; ++j)
+            if (j < ng) {
+                wpsi += W * (double)psi[j];
+                if (a.psi_exit) a.psi_exit[hook + j] = (double)psi[j];
+            }
+        s_out = wpsi;
         const Bound b = boundary_of(base, c, Lt, a.H, dir, true, meta);
         if (is_vacuum(a, b)) {
-            leak = W * (double)psi;
+            leak = wpsi;
         } else if (a.psi_out) {
             const long long slot2 = successor_slot(a, b, t, n, dir, base, c);
-            if (slot2 >= 0) ((B *)a.psi_out)[slot2 * G + g] = (B)psi;
-            else {
+            if (slot2 >= 0) {
+#pragma unroll
+                for (int j = 0; j < kGL; ++j)
+                    if (j < ng) ((B *)a.psi_out)[slot2 * G + g0 + j] = (B)psi[j];
+            } else {
                 link_err = 1;
-                leak = W * (double)psi;
+                leak = wpsi;
             }
         }
     }
     const double v_in = wave_sum(s_in), v_out = wave_sum(s_out), v_lk = wave_sum(leak);
-    const long long ns = wave_sum_ll(active ? nseg : 0);
+    const long long ns = wave_sum_ll(active ? nseg * ng : 0);
     const long long le_ = wave_sum_ll(link_err);
     if (lane == 0) {
         const int sl = (int)(w % kSlots);
@@ -366,7 +391,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
 // collects W * delta_psi from every line of every polar stack that crosses
 // the window; the tally is then added to HBM with one atomic per touched
 // FSR-group.  Waves take bundles of T consecutive lines of one stack (lane =
-// line x group) and walk the window's segments in lockstep.  A line's angular
+// line x group chunk) and walk the window's segments in lockstep.  A line's angular
 // flux is carried from window to window in its own boundary slot (read once
 // at its start, then free); a line starting on a vacuum face starts from 0.
 constexpr int kWinThreads = 512;
@@ -383,15 +408,26 @@ __host__ __device__ inline size_t win_lds_bytes(int Sw, int K, int G, int rbytes
 
 
 __device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline float uniform_val(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ inline double uniform_val(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffff));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 
 // MODE 0: transport sweep; MODE 1: volume tally (W l / 4 pi per FSR).
 // EXPM 0: stable 1 - e^-tau; EXPM 1: 1 - hardware exp (precision study).
-template <typename R, typename B, int MODE, int EXPM, bool BWD>
+template <typename R, typename B, int MODE, int EXPM, bool BWD, bool C1>
 __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit,
                                            unsigned char *smem) {
     const SweepArgs &a = wa.s;
     const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6);
     const int G = a.G, K = a.K, P = a.P, T = a.T;
+    // C1: all groups of a line in one lane (G <= kGL), the common case
+    const int C = C1 ? 1 : a.C, GL = C1 ? a.G : a.GL;
     const int KG = K * G;
     const int Sw = wa.Sw;
     // LDS: [line ranges | FP64 tally Sw*KG | segment starts Sw+1 |
@@ -416,8 +452,10 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
     const long long fi0 = wa.filt_i0 ? wa.filt_i0[unit] : 0;
     const R *sigt = (const R *)a.sigt;
     const R *qhat = (const R *)a.qhat;
-    const int tr = lane / G;
-    const int g = lane - tr * G;
+    // lane = (line tr of the bundle, group chunk): groups g0 .. g0+ng-1
+    const int tr = C == 1 ? lane : lane / C;
+    const int g0 = (lane - tr * C) * GL;
+    const int ng = max(0, min(GL, G - g0));
 
     for (int i = tid; i < Sw * KG; i += kWinThreads) acc_l[i] = 0.0;
 
@@ -504,7 +542,7 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
             const int an = az * P + n;
             const double c = a.cot[an], secl = a.secl[an], W = a.wgt[an];
             const int i = uniform(r_lo[n] + (bnd - bpre[n]) * T) + tr;
-            const bool active = (tr < T) && (i <= r_hi[n]);
+            const bool active = (tr < T) && (i <= r_hi[n]) && ng > 0;
             const double base = line_base(a, s, i);
             double ls = 1e300, le = -1e300;
             if (active) clip_line(base, c, Lt, a.H, ls, le);
@@ -523,15 +561,26 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
             const bool starts = dir == 0 ? (ls >= wa_) : (le <= wb_);
             const bool ends = dir == 0 ? (le <= wb_) : (ls >= wa_);
             const long long slot = 2 * (a.trk_off[s] + i) + dir;
-            R psi = 0;
+            const size_t hook = (size_t)unit * kItemStride + (size_t)(i - fi0) * G + g0;
+            R psi[kGL];
+#pragma unroll
+            for (int j = 0; j < kGL; ++j) psi[j] = 0;
             if (MODE == 0 && active) {
+                const B *pin = (const B *)a.psi_in + slot * G + g0;
                 if (!starts) {
-                    psi = (R)((const B *)a.psi_in)[slot * G + g];
+#pragma unroll
+                    for (int j = 0; j < kGL; ++j)
+                        if (j < ng) psi[j] = (R)pin[j];
                 } else {
-                    if (a.psi_entry) psi = (R)a.psi_entry[(size_t)unit * 64 + (i - fi0) * G + g];
-                    else if (!is_vacuum(a, boundary_of(base, c, Lt, a.H, dir, false, meta)))
-                        psi = (R)((const B *)a.psi_in)[slot * G + g];
-                    s_in += W * (double)psi;
+                    const bool from_vacuum =
+                        !a.psi_entry && is_vacuum(a, boundary_of(base, c, Lt, a.H, dir, false, meta));
+#pragma unroll
+                    for (int j = 0; j < kGL; ++j)
+                        if (j < ng) {
+                            if (a.psi_entry) psi[j] = (R)a.psi_entry[hook + j];
+                            else if (!from_vacuum) psi[j] = (R)pin[j];
+                            s_in += W * (double)psi[j];
+                        }
                 }
             }
             Walker wk;
@@ -543,41 +592,70 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                 if (!active) continue;
                 const double e = dir ? fmax(s0, ls) : fmin(s1, le);
                 if (!(dir ? e < wk.lcur : e > wk.lcur)) continue;
-                const int lb = kk * KG + g;
+                const int lb = kk * KG + g0;
                 if (MODE == 1) {
                     nseg += walk_segment<BWD>(wk, e, secl, K, [&](int kz, double l3, bool valid) {
-                        if (g == 0 && valid)
+                        if (g0 == 0 && valid)
                             __hip_atomic_fetch_add(&acc_l[lb + kz * G], W * l3 / kFourPi, __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_WORKGROUP);
                     });
                     continue;
                 }
-                const R st = s_st[kk * G + g];
+                // Sigma_t of the segment's material for the lane's groups (the
+                // same for every lane when C1: held in scalar registers).  The
+                // group loop bound GL is uniform; a lane of the last chunk with
+                // fewer groups repeats its last group with a zero update.
+                R stv[kGL];
+#pragma unroll
+                for (int j = 0; j < kGL; ++j)
+                    if (j < GL) stv[j] = C1 ? uniform_val(s_st[kk * G + j]) : s_st[kk * G + g0 + min(j, ng - 1)];
                 nseg += walk_segment<BWD>(wk, e, secl, K, [&](int kz, double l3, bool valid) {
                     const int li = lb + kz * G;
-                    // a piece below kMinSeg adds nothing: F = 0 keeps psi unchanged
-                    const R F = valid ? one_minus_exp<R>(st * (R)l3, EXPM) : (R)0;
-                    const R d = (psi - q_l[li]) * F;
-                    psi -= d;                                                      // Eq. 3
-                    __hip_atomic_fetch_add(&acc_l[li], W * (double)d, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                    // a piece below kMinSeg adds nothing: F(0) = 0 keeps psi unchanged
+                    const R lr = valid ? (R)l3 : (R)0;
+                    R qv[kGL];
+#pragma unroll
+                    for (int j = 0; j < kGL; ++j)
+                        if (j < GL) qv[j] = q_l[li + (C1 ? j : min(j, ng - 1))];
+#pragma unroll
+                    for (int j = 0; j < kGL; ++j)
+                        if (j < GL) {
+                            R d = (psi[j] - qv[j]) * one_minus_exp<R>(stv[j] * lr, EXPM);
+                            if (!C1 && j >= ng) d = (R)0;
+                            psi[j] -= d;                                           // Eq. 3
+                            __hip_atomic_fetch_add(&acc_l[li + (C1 ? j : min(j, ng - 1))], W * (double)d,
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        }
                 });
             }
             if (MODE == 0 && active) {
                 if (!ends) {
-                    ((B *)a.psi_in)[slot * G + g] = (B)psi;        // carried to the next window
+                    B *pc = (B *)a.psi_in + slot * G + g0;          // carried to the next window
+#pragma unroll
+                    for (int j = 0; j < kGL; ++j)
+                        if (j < ng) pc[j] = (B)psi[j];
                 } else {
-                    s_out += W * (double)psi;
-                    if (a.psi_exit) a.psi_exit[(size_t)unit * 64 + (i - fi0) * G + g] = (double)psi;
+                    double wpsi = 0.0;
+#pragma unroll
+                    for (int j = 0; j < kGL; ++j)
+                        if (j < ng) {
+                            wpsi += W * (double)psi[j];
+                            if (a.psi_exit) a.psi_exit[hook + j] = (double)psi[j];
+                        }
+                    s_out += wpsi;
                     const Bound b = boundary_of(base, c, Lt, a.H, dir, true, meta);
                     if (is_vacuum(a, b)) {
-                        leak += W * (double)psi;
+                        leak += wpsi;
                     } else if (a.psi_out) {
                         const long long slot2 = successor_slot(a, b, t, n, dir, base, c);
-                        if (slot2 >= 0) ((B *)a.psi_out)[slot2 * G + g] = (B)psi;
-                        else {
+                        if (slot2 >= 0) {
+                            B *po = (B *)a.psi_out + slot2 * G + g0;
+#pragma unroll
+                            for (int j = 0; j < kGL; ++j)
+                                if (j < ng) po[j] = (B)psi[j];
+                        } else {
                             ++link_err;
-                            leak += W * (double)psi;
+                            leak += wpsi;
                         }
                     }
                 }
@@ -601,7 +679,7 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
     }
     // per-wave totals -> spread scalar slots
     const double v_in = wave_sum(s_in), v_out = wave_sum(s_out), v_lk = wave_sum(leak);
-    const long long ns = wave_sum_ll(MODE == 1 ? (g == 0 ? nseg : 0) : nseg);
+    const long long ns = wave_sum_ll(MODE == 1 ? (g0 == 0 ? nseg : 0) : nseg * ng);
     const long long le_ = wave_sum_ll(link_err);
     if (lane == 0) {
         const int sl = (int)(((long long)unit * kWinWaves + wave) % kSlots);
@@ -615,30 +693,43 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
     }
 }
 
-template <typename R, typename B, int MODE, int EXPM>
-__global__ __launch_bounds__(kWinThreads) void k_sweep_win(WinArgs wa) {
+// FP32 arithmetic: capped at 128 VGPRs so that two 512-thread workgroups
+// share a CU (4 waves per SIMD).  C1: G <= 8, all groups of a line in one lane.
+template <typename B, int MODE, int EXPM, bool C1>
+__global__ __launch_bounds__(kWinThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_win(WinArgs wa) {
     extern __shared__ __align__(16) unsigned char smem[];
     // the direction is uniform per workgroup: specialise the whole unit on it
     const int code = wa.work[blockIdx.x];
-    if (code & 1) sweep_unit<R, B, MODE, EXPM, true>(wa, code, blockIdx.x, smem);
-    else sweep_unit<R, B, MODE, EXPM, false>(wa, code, blockIdx.x, smem);
+    if (code & 1) sweep_unit<float, B, MODE, EXPM, true, C1>(wa, code, blockIdx.x, smem);
+    else sweep_unit<float, B, MODE, EXPM, false, C1>(wa, code, blockIdx.x, smem);
 }
 
-// Batched form for serving: work unit u belongs to problem slot u_slot[u] and
-// is (2D track, direction) u_code[u] of that problem; every problem brings its
-// own descriptor (pointers into its own workspace, sizes, window length), so
-// the units of all active problems run in one launch.
-__global__ __launch_bounds__(kWinThreads) void k_sweep_win_multi(const WinArgs *__restrict__ descs,
-                                                                  const int *__restrict__ u_slot,
-                                                                  const int *__restrict__ u_code) {
+// FP64 arithmetic (precision reference): no register cap
+template <typename B, int MODE, bool C1>
+__global__ __launch_bounds__(kWinThreads) void k_sweep_win_f64(WinArgs wa) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int slot = u_slot[blockIdx.x];
-    const int code = u_code[blockIdx.x];
+    const int code = wa.work[blockIdx.x];
+    if (code & 1) sweep_unit<double, B, MODE, 0, true, C1>(wa, code, blockIdx.x, smem);
+    else sweep_unit<double, B, MODE, 0, false, C1>(wa, code, blockIdx.x, smem);
+}
+
+// Batched form for serving: work unit u0 + b belongs to problem slot
+// u_slot[u0 + b] and is (2D track, direction) u_code[u0 + b] of that problem;
+// every problem brings its own descriptor (pointers into its own workspace,
+// sizes, window length), so the units of all active problems run in one
+// launch (one launch per lane layout).
+template <bool C1>
+__global__ __launch_bounds__(kWinThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_win_multi(
+    const WinArgs *__restrict__ descs, const int *__restrict__ u_slot, const int *__restrict__ u_code,
+    int u0) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int slot = u_slot[u0 + blockIdx.x];
+    const int code = u_code[u0 + blockIdx.x];
     // descriptors are never written during the launch (restrict): their
     // fields load once instead of after every store to the tallies
     const WinArgs &wa = descs[slot];
-    if (code & 1) sweep_unit<float, float, 0, 0, true>(wa, code, blockIdx.x, smem);
-    else sweep_unit<float, float, 0, 0, false>(wa, code, blockIdx.x, smem);
+    if (code & 1) sweep_unit<float, float, 0, 0, true, C1>(wa, code, blockIdx.x, smem);
+    else sweep_unit<float, float, 0, 0, false, C1>(wa, code, blockIdx.x, smem);
 }
 
 // ------------------------------------------------------------------ trace hook
@@ -863,6 +954,8 @@ SweepArgs Solver::sweep_args(int fp64, int exp_mode) const {
     a.P = P;
     a.K = K;
     a.T = info.tracks_per_wave;
+    a.C = group_chunks(a.G);
+    a.GL = groups_per_lane(a.G);
     std::memcpy(a.bc, bc, sizeof(a.bc));
     a.exp_mode = exp_mode;
     return a;
@@ -974,11 +1067,24 @@ int Solver::compute_volumes() {
     return MOC_OK;
 }
 
+template <typename R, typename B, bool C1>
+static void launch_win_c(const WinArgs &wa, unsigned nb, size_t lds, hipStream_t st, int mode, int expm) {
+    if (std::is_same<R, double>::value) {
+        if (mode == 1) k_sweep_win_f64<B, 1, C1><<<nb, kWinThreads, lds, st>>>(wa);
+        else k_sweep_win_f64<B, 0, C1><<<nb, kWinThreads, lds, st>>>(wa);
+    } else if (mode == 1) {
+        k_sweep_win<B, 1, 0, C1><<<nb, kWinThreads, lds, st>>>(wa);
+    } else if (expm == 0) {
+        k_sweep_win<B, 0, 0, C1><<<nb, kWinThreads, lds, st>>>(wa);
+    } else {
+        k_sweep_win<B, 0, 1, C1><<<nb, kWinThreads, lds, st>>>(wa);
+    }
+}
+
 template <typename R, typename B>
 static void launch_win(const WinArgs &wa, unsigned nb, size_t lds, hipStream_t st, int mode, int expm) {
-    if (mode == 1) k_sweep_win<R, B, 1, 0><<<nb, kWinThreads, lds, st>>>(wa);
-    else if (expm == 0) k_sweep_win<R, B, 0, 0><<<nb, kWinThreads, lds, st>>>(wa);
-    else k_sweep_win<R, B, 0, 1><<<nb, kWinThreads, lds, st>>>(wa);
+    if (wa.s.C == 1) launch_win_c<R, B, true>(wa, nb, lds, st, mode, expm);
+    else launch_win_c<R, B, false>(wa, nb, lds, st, mode, expm);
 }
 
 void Solver::launch_sweep(SweepArgs a, bool fp64, const int *units, int n_units,
@@ -1070,8 +1176,11 @@ int launch_batch_step(const BatchStep &b, hipStream_t st) {
     if (b.n_slots <= 0) return MOC_OK;
     k_clear_scal_multi<<<dim3(8, b.n_slots), 256, 0, st>>>(b.fsr_table, 128 * 1024 / 4);
     k_source_multi<<<b.fsr_blocks, 256, 0, st>>>(b.fsr_table, b.blk_pre, b.n_slots);
-    if (b.n_units > 0)
-        k_sweep_win_multi<<<b.n_units, kWinThreads, b.lds, st>>>(b.win_table, b.u_slot, b.u_code);
+    if (b.n_units_c1 > 0)
+        k_sweep_win_multi<true><<<b.n_units_c1, kWinThreads, b.lds, st>>>(b.win_table, b.u_slot, b.u_code, 0);
+    if (b.n_units > b.n_units_c1)
+        k_sweep_win_multi<false><<<b.n_units - b.n_units_c1, kWinThreads, b.lds, st>>>(
+            b.win_table, b.u_slot, b.u_code, b.n_units_c1);
     k_finalize_multi<<<b.fsr_blocks, 256, 0, st>>>(b.fsr_table, b.blk_pre, b.n_slots);
     k_gather_residual<<<(b.n_slots + 255) / 256, 256, 0, st>>>(b.fsr_table, b.n_slots, b.res_dev);
     HIPCHK(hipGetLastError());
@@ -1193,12 +1302,12 @@ int Solver::sweep_items(long long n_items, const long long *items, const double 
     std::vector<long long> fi0;
     for (long long b = 0; b < n_items; b += (long long)cap) {
         const long long nb = std::min<long long>(cap, n_items - b);
-        ent.assign(nb * 64, 0.0);
+        ent.assign(nb * kItemStride, 0.0);
         for (long long w = 0; w < nb; ++w)
             for (int tr = 0; tr < T; ++tr)
                 for (int g = 0; g < G; ++g)
-                    ent[w * 64 + tr * G + g] = psi_in[((b + w) * T + tr) * G + g];
-        HIPCHK(hipMemcpyAsync(entry, ent.data(), nb * 64 * 8, hipMemcpyHostToDevice, stream));
+                    ent[w * kItemStride + tr * G + g] = psi_in[((b + w) * T + tr) * G + g];
+        HIPCHK(hipMemcpyAsync(entry, ent.data(), nb * kItemStride * 8, hipMemcpyHostToDevice, stream));
         SweepArgs a = sweep_args(fp64, 0);
         a.psi_in = ws + lay.off_psi0;      // scratch for flux carried between windows
         a.psi_out = nullptr;
@@ -1230,13 +1339,13 @@ int Solver::sweep_items(long long n_items, const long long *items, const double 
             launch_sweep(a, fp64 != 0);
         }
         HIPCHK(hipGetLastError());
-        ex.assign(nb * 64, 0.0);
-        HIPCHK(hipMemcpyAsync(ex.data(), exitb, nb * 64 * 8, hipMemcpyDeviceToHost, stream));
+        ex.assign(nb * kItemStride, 0.0);
+        HIPCHK(hipMemcpyAsync(ex.data(), exitb, nb * kItemStride * 8, hipMemcpyDeviceToHost, stream));
         HIPCHK(hipStreamSynchronize(stream));
         for (long long w = 0; w < nb; ++w)
             for (int tr = 0; tr < T; ++tr)
                 for (int g = 0; g < G; ++g)
-                    psi_out[((b + w) * T + tr) * G + g] = ex[w * 64 + tr * G + g];
+                    psi_out[((b + w) * T + tr) * G + g] = ex[w * kItemStride + tr * G + g];
     }
     HIPCHK(hipMemcpyAsync(acc_out, ws + lay.off_acc, nfg * 8, hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
