@@ -218,6 +218,13 @@ MOC_API int moc_sweep_items(moc_solver *s, long long n_items, const long long *i
 MOC_API int moc_trace_tracks(moc_solver *s, long long n, const long long *track_ids, int cap,
                              int *fsr_out, double *len_out, int *count_out);
 
+/* Test hook: the sweep's FP32 attenuation factor F(tau) = 1 - exp(-tau) of
+ * Eq. 3, evaluated on the device by the same device function the sweep uses
+ * (exp_mode 0: stable form; 1: naive 1 - exp) for n host values tau >= 0;
+ * FP32 results to the host array out [n].  Allocates and frees its own
+ * device buffers (not part of the solve path); synchronous. */
+MOC_API int moc_eval_attenuation(const float *tau, long long n, int exp_mode, float *out);
+
 /* ---------------------------------------------------------------- serving */
 
 /* Continuous batching of independent fixed-source solves on one GPU (the

@@ -265,4 +265,13 @@ int moc_trace_tracks(moc_solver *sv, long long n, const long long *track_ids, in
     return s.trace_tracks(n, track_ids, cap, fsr_out, len_out, count_out);
 }
 
+int moc_eval_attenuation(const float *tau, long long n, int exp_mode, float *out) {
+    if (n < 0 || (n > 0 && (!tau || !out))) return fail(MOC_EINVAL, "NULL argument or n < 0");
+    if (exp_mode != 0 && exp_mode != 1) return fail(MOC_EINVAL, "exp_mode must be 0 or 1");
+    if (n > (1LL << 28)) return fail(MOC_EINVAL, "n too large (at most 2^28)");
+    for (long long i = 0; i < n; ++i)
+        if (!(tau[i] >= 0.0f) || !std::isfinite(tau[i])) return fail(MOC_EINVAL, "tau must be finite and >= 0");
+    return moc::eval_attenuation(tau, n, exp_mode, out);
+}
+
 }  // extern "C"

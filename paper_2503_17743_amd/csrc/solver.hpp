@@ -27,6 +27,8 @@ struct BatchStep {
     size_t lds;                 // dynamic LDS of the batched sweep (max over problems)
 };
 int launch_batch_step(const BatchStep &b, hipStream_t st);
+// test hook: the sweep's F(tau) on the device for host values
+int eval_attenuation(const float *tau, long long n, int exp_mode, float *out);
 // 2D segments per LDS window of the windowed sweep (0: does not fit)
 int window_fit(const Plan &p, bool fp64);
 

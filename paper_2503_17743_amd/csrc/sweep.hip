@@ -732,6 +732,35 @@ __global__ __launch_bounds__(kWinThreads) __attribute__((amdgpu_waves_per_eu(4))
     else sweep_unit<float, float, 0, 0, false, C1>(wa, code, blockIdx.x, smem);
 }
 
+// ------------------------------------------------------------------ F(tau) hook
+
+__global__ void k_eval_attenuation(const float *tau, float *out, long long n, int exp_mode) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = one_minus_exp<float>(tau[i], exp_mode);
+}
+
+int eval_attenuation(const float *tau, long long n, int exp_mode, float *out) {
+    if (n <= 0) return MOC_OK;
+    float *d = nullptr;
+    hipError_t e = hipMalloc((void **)&d, (size_t)n * 8);
+    if (e != hipSuccess) {
+        set_error(hipGetErrorString(e));
+        return MOC_ENOMEM;
+    }
+    e = hipMemcpy(d, tau, (size_t)n * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        k_eval_attenuation<<<(unsigned)((n + 255) / 256), 256>>>(d, d + n, n, exp_mode);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpy(out, d + n, (size_t)n * 4, hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    if (e != hipSuccess) {
+        set_error(hipGetErrorString(e));
+        return MOC_EDEVICE;
+    }
+    return MOC_OK;
+}
+
 // ------------------------------------------------------------------ trace hook
 
 // One thread per requested stored track (forward): the same piece generation

@@ -103,6 +103,7 @@ def lib():
         "moc_server_create": ([VP, C.c_size_t, C.c_int, VP, C.POINTER(VP)], C.c_int),
         "moc_server_destroy": ([VP], None),
         "moc_server_arena_overhead": ([C.c_int, C.POINTER(C.c_size_t)], C.c_int),
+        "moc_eval_attenuation": ([VP, C.c_longlong, C.c_int, VP], C.c_int),
         "moc_server_submit": ([VP, VP, VP, C.POINTER(SolveOpts), C.POINTER(C.c_ulonglong)], C.c_int),
         "moc_server_step": ([VP, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
         "moc_server_poll": ([VP, C.c_ulonglong, C.POINTER(Stats), VP, C.c_size_t], C.c_int),
@@ -357,3 +358,11 @@ def solve(prob, tol=None, max_iters=None, sweep_fp64=False, exp_mode=0):
     return s.solve(tol=prob.tol if tol is None else tol,
                    max_iters=prob.max_iters if max_iters is None else max_iters,
                    sweep_fp64=sweep_fp64, exp_mode=exp_mode)
+
+
+def eval_attenuation(tau, exp_mode=0):
+    """The sweep's FP32 F(tau) = 1 - exp(-tau), evaluated on the device."""
+    t = np.ascontiguousarray(tau, dtype=np.float32)
+    out = np.empty_like(t)
+    _check(lib().moc_eval_attenuation(_p(t), t.size, int(exp_mode), _p(out)))
+    return out

@@ -1,0 +1,133 @@
+"""Precision and scale studies on the large lattices; one JSON line each.
+
+  python -m paper_2503_17743_amd.study precision [--workload lattice32] [--iters 20]
+      The same iterate of the FP32 sweep (stable and naive 1 - exp) and of the
+      FP64 sweep from phi = 0; per-FSR-group relative error of each FP32 variant
+      against the FP64 sweep.
+  python -m paper_2503_17743_amd.study scale [--workload lattice64] [--iters 50]
+      FP32 source iterations of the whole problem: time per sweep, residual
+      history and the neutron balance of the last iteration.
+
+Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import moc, problems as P
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _rel_stats(phi, ref):
+    m = np.abs(ref) > 0
+    r = np.abs(phi[m] - ref[m]) / np.abs(ref[m])
+    return {"max": float(r.max()), "p999": float(np.percentile(r, 99.9)),
+            "p50": float(np.percentile(r, 50)), "n": int(m.sum())}
+
+
+def precision(name, iters, fp64_boundary=None):
+    import torch
+    prob = P.get(name)
+    plan = moc.Plan(prob)
+    if fp64_boundary is None:
+        free, _ = torch.cuda.mem_get_info()
+        fp64_boundary = plan.info["workspace_bytes_fp64"] < 0.8 * free
+    s = moc.Solver(plan, fp64_boundary=fp64_boundary)
+    s.set_source(prob.q)
+    runs = {}
+    for label, kw in (("fp64_sweep", dict(sweep_fp64=True)), ("fp32_stable", dict()),
+                      ("fp32_naive_exp", dict(exp_mode=1))):
+        _log(f"precision {name}: {label}, {iters} iterations ...")
+        s.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = s.iterate(iters, **kw)
+        torch.cuda.synchronize()
+        runs[label] = (s.flux(), st, time.perf_counter() - t0)
+    if fp64_boundary:
+        # the production configuration: FP32 sweep with FP32 boundary storage
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        s = moc.Solver(plan, fp64_boundary=False)
+        s.set_source(prob.q)
+        _log(f"precision {name}: fp32_stable with FP32 boundary storage ...")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = s.iterate(iters)
+        torch.cuda.synchronize()
+        runs["fp32_stable_fp32_boundary"] = (s.flux(), st, time.perf_counter() - t0)
+    ref = runs["fp64_sweep"][0]
+    out = {"study": "precision", "workload": name, "iterations": iters,
+           "fp64_boundary_storage": bool(fp64_boundary),
+           "seg_group_updates_per_sweep": runs["fp32_stable"][1]["seg_group_updates"]}
+    for label, (phi, st, t) in runs.items():
+        d = {"sweep_ms_median": st["sweep_ms_median"], "wall_s": t, "residual": st["residual"],
+             "balance_rel": abs(st["balance_lhs"] - st["balance_rhs"]) / max(abs(st["balance_rhs"]), 1e-300)}
+        if label != "fp64_sweep":
+            d["rel_err_vs_fp64_sweep"] = _rel_stats(phi, ref)
+        out[label] = d
+    s.close()
+    return out
+
+
+def scale(name, iters):
+    import torch
+    prob = P.get(name)
+    t0 = time.perf_counter()
+    plan = moc.Plan(prob)
+    t_plan = time.perf_counter() - t0
+    _log(f"scale {name}: planned in {t_plan:.1f} s, workspace {plan.info['workspace_bytes'] / 1e9:.1f} GB")
+    s = moc.Solver(plan, fp64_boundary=False)
+    s.set_source(prob.q)
+    torch.cuda.synchronize()
+    hist, sweep_ms = [], []
+    t0 = time.perf_counter()
+    st = None
+    for k in range(iters):
+        st = s.iterate(1)
+        hist.append(st["residual"])
+        sweep_ms.append(st["sweep_ms_median"])
+        _log(f"scale {name}: iteration {k + 1}/{iters} residual {st['residual']:.3e} "
+             f"sweep {st['sweep_ms_median']:.1f} ms")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    segg = st["seg_group_updates"]
+    med = float(np.median(sweep_ms))
+    out = {"study": "scale", "workload": name, "iterations": iters, "plan_s": t_plan,
+           "n_fsr": plan.info["n_fsr"], "n_3d_tracks": plan.info["n_3d_tracks"],
+           "workspace_bytes": plan.info["workspace_bytes"],
+           "seg_group_updates_per_sweep": segg, "sweep_ms_median": med,
+           "seg_group_per_s_sweep": segg / (med * 1e-3),
+           "seg_group_per_s_wall": segg * iters / wall, "wall_s": wall,
+           "residual_history": hist, "link_errors": st["link_errors"],
+           "balance_rel": abs(st["balance_lhs"] - st["balance_rhs"]) / max(abs(st["balance_rhs"]), 1e-300)}
+    s.close()
+    return out
+
+
+def main(argv=None):
+    import torch
+    ap = argparse.ArgumentParser()
+    ap.add_argument("study", choices=("precision", "scale"))
+    ap.add_argument("--workload", default=None)
+    ap.add_argument("--iters", type=int, default=None)
+    args = ap.parse_args(argv)
+    torch.cuda.set_device(0)
+    if args.study == "precision":
+        out = precision(args.workload or "lattice32", args.iters or 20)
+    else:
+        out = scale(args.workload or "lattice64", args.iters or 50)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

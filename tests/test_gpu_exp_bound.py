@@ -1,0 +1,68 @@
+"""The sweep's FP32 attenuation factor F(tau) = 1 - exp(-tau) (Eq. 3) against
+FP64 expm1: the stable form is within 4 ulp over tau in [2^-30, 40]; the naive
+1 - exp form loses relative accuracy like eps/tau for small tau."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+STABLE_ULP_BOUND = 4.0
+
+
+@pytest.fixture(scope="module")
+def moc():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2503_17743_amd import moc as M
+    M.lib()
+    return M
+
+
+def _taus():
+    rng = np.random.default_rng(7)
+    dense = np.logspace(-30 * np.log10(2), np.log10(40.0), 400_000)
+    # around the switch between the two evaluation branches and the ends
+    edges = np.concatenate([np.linspace(0.45, 0.55, 20_001), [2.0 ** -30, 40.0, 0.5]])
+    rand = rng.uniform(0.0, 3.0, 200_000)
+    t = np.concatenate([dense, edges, rand]).astype(np.float32)
+    return t[(t >= 2.0 ** -30) & (t <= 40.0)]
+
+
+def _ulp_error(got, tau):
+    ref = -np.expm1(-tau.astype(np.float64))
+    ulp = np.spacing(ref.astype(np.float32)).astype(np.float64)
+    return np.abs(got.astype(np.float64) - ref) / ulp, ref
+
+
+def test_stable_attenuation_within_4_ulp(moc):
+    tau = _taus()
+    got = moc.eval_attenuation(tau, exp_mode=0)
+    err, _ = _ulp_error(got, tau)
+    worst = int(np.argmax(err))
+    print(f"stable F: max {err.max():.2f} ulp at tau={tau[worst]:.6g} over {tau.size} points")
+    assert err.max() <= STABLE_ULP_BOUND
+
+
+def test_naive_attenuation_loses_small_tau(moc):
+    tau = np.array([1e-7, 1e-5, 1e-3], np.float32)
+    got = moc.eval_attenuation(tau, exp_mode=1)
+    _, ref = _ulp_error(got, tau)
+    rel = np.abs(got - ref) / ref
+    # cancellation: the absolute error is ~ ulp(1) = 6e-8, i.e. ~ 6e-8 / tau relative
+    assert rel[0] > 1e-2
+    # the stable form at the same points stays within the bound
+    err, _ = _ulp_error(moc.eval_attenuation(tau, exp_mode=0), tau)
+    assert err.max() <= STABLE_ULP_BOUND
+
+
+def test_attenuation_special_values(moc):
+    tau = np.array([0.0, 2.0 ** -149, 88.0, 200.0], np.float32)
+    got = moc.eval_attenuation(tau, exp_mode=0)
+    assert got[0] == 0.0
+    assert 0.0 <= got[1] <= 2.0 ** -148
+    assert got[2] == 1.0 and got[3] == 1.0
+
+
+def test_rejects_negative_tau(moc):
+    with pytest.raises(moc.MocError):
+        moc.eval_attenuation(np.array([-1.0], np.float32))
