@@ -111,11 +111,13 @@ typedef struct {
     size_t psi_bytes;          /* of which: the two boundary angular-flux buffers  */
     size_t workspace_bytes_fp64; /* bytes for FP64 boundary flux (needed by the    */
                                  /* FP64 sweep to keep full precision)             */
+    int line_stride;           /* lines between neighbouring lanes of a sweep bundle */
 } moc_plan_info;
 
 /* Solve controls.  sweep_fp64 = 1 runs segment arithmetic and angular flux in
- * FP64 (precision study); exp_mode 0 = stable 1-e^-tau via expm1, 1 = the
- * naive 1 - exp(-tau) with the hardware exponential (precision study only). */
+ * FP64 (precision study); exp_mode 0 = stable 1 - e^-tau (polynomial below
+ * tau = 1/2, hardware exp2 above; within 4 ulp), 1 = the naive 1 - exp(-tau)
+ * with the hardware exponential (precision study only). */
 typedef struct {
     double tol;                /* stop when the L-inf relative flux change < tol  */
     int max_iters;

@@ -5,7 +5,7 @@
 namespace moc {
 
 struct SweepArgs {
-    const double *cot, *secl, *seca, *wgt;       // [A2][P]
+    const double *cot, *icot, *secl, *wgt;       // [A2][P]: cot, 1/cot, 1/sin, weight
     const double *t_len;                          // [n2d]
     const int *t_first, *t_meta, *t_link;         // [n2d+1], [n2d], [2*n2d]
     const double *seg_pos;                        // [nseg]
@@ -25,7 +25,7 @@ struct SweepArgs {
     long long n_items;
     long long n_stacks;
     double *scal;
-    double H, h, inv_h, dz;
+    double H, h, inv_h, dz, inv_dz;
     int G, P, K, T;
     int C, GL;                                    // group chunks across lanes, groups per lane
     int bc[6];
@@ -39,6 +39,7 @@ struct WinArgs {
     const int *filt_n;        // test hook: only this polar stack per unit (or null)
     const long long *filt_i0; // test hook: only lines [i0, i0+T) of it
     int Sw;                   // 2D segments per window
+    int lstride;              // line stride inside a bundle (1: consecutive lines)
 };
 
 struct FsrArgs {

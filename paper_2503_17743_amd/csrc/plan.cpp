@@ -466,6 +466,14 @@ std::string Plan::build(const moc_geometry &g, const moc_tracking &t, const moc_
         }
     }
     T = 64 / group_chunks(G);
+    // line stride of the windowed sweep's bundles: lanes one layer apart
+    // (h/dz lines) when every stack has enough lines at any 2D position
+    // (about H/dz) to keep bundles of stride * T lines mostly full
+    {
+        const int per_layer = std::max(1, (int)std::floor(h / dz + 1e-9));
+        const int deep = (int)(H / dz / (4.0 * T));
+        lstride = std::max(1, std::min(per_layer, deep));
+    }
     trk_off.assign(n_stacks + 1, 0);
     chunk_off.assign(n_stacks + 1, 0);
     for (int64_t s = 0; s < n_stacks; ++s) {
@@ -489,6 +497,7 @@ moc_plan_info Plan::info() const {
     o.n_chunks = n_chunks;
     o.n_groups = G;
     o.tracks_per_wave = T;
+    o.line_stride = lstride;
     o.dz = dz;
     Layout l = make_layout(*this, false);
     o.workspace_bytes = l.total;
@@ -509,7 +518,7 @@ Layout make_layout(const Plan &p, bool psi64) {
     size_t ap = (size_t)p.A2 * p.P;
     l.off_cot = take(ap * 8);
     l.off_secl = take(ap * 8);
-    l.off_seca = take(ap * 8);
+    l.off_icot = take(ap * 8);
     l.off_wgt = take(ap * 8);
     l.off_t_len = take(p.n2d * 8);
     l.off_t_first = take((p.n2d + 1) * 4);

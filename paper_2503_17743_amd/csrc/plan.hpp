@@ -62,6 +62,7 @@ struct Plan {
     // ---- z-stacks (s = t*P + n) ----
     int64_t n_stacks = 0, n3d = 0, n_chunks = 0;
     int T = 1;                                 // tracks per wave (bundle size)
+    int lstride = 1;                           // line stride inside a bundle
     std::vector<double> zeta;
     std::vector<int64_t> ilo, cnt, trk_off, chunk_off;   // trk_off/chunk_off: [n_stacks+1]
 
@@ -72,7 +73,7 @@ struct Plan {
 // Device layout of a plan inside a caller workspace.
 struct Layout {
     size_t total = 0;
-    size_t off_cot = 0, off_secl = 0, off_seca = 0, off_wgt = 0;  // [A2][P] doubles
+    size_t off_cot = 0, off_secl = 0, off_icot = 0, off_wgt = 0;  // [A2][P] doubles
     size_t off_t_len = 0, off_t_first = 0, off_t_meta = 0, off_t_link = 0;
     size_t off_seg_pos = 0, off_seg_reg = 0, off_reg_mat = 0;
     size_t off_zeta = 0, off_ilo = 0, off_cnt = 0, off_trk_off = 0, off_chunk_off = 0;

@@ -49,6 +49,7 @@ struct Solver {
     std::vector<float> sweep_ms;
     std::vector<hipEvent_t> events;
     int sw32 = 0, sw64 = 0;          // windowed sweep: 2D segments per window (0: direct path)
+    int lstride = 1;                 // windowed sweep: line stride inside a bundle
     std::vector<long long> chunk_off, trk_off;
     std::vector<int> work_host;      // windowed-sweep work list (longest first)
     std::vector<float> work_cost;    // estimated cost of each work-list unit

@@ -98,16 +98,16 @@ __device__ inline long long wave_sum_ll(long long v) {
 }
 
 // 2D-length interval [ls, le] of the line z = base + c l inside the box
-// (0 <= l <= Lt, 0 <= z <= H)
-__device__ inline void clip_line(double base, double c, double Lt, double H, double &ls,
+// (0 <= l <= Lt, 0 <= z <= H); ic = 1/c
+__device__ inline void clip_line(double base, double c, double ic, double Lt, double H, double &ls,
                                  double &le) {
     double a, b;
     if (c > 0) {
-        a = -base / c;
-        b = (H - base) / c;
+        a = -base * ic;
+        b = (H - base) * ic;
     } else {
-        a = (H - base) / c;
-        b = -base / c;
+        a = (H - base) * ic;
+        b = -base * ic;
     }
     ls = a > 0 ? a : 0.0;
     le = b < Lt ? b : Lt;
@@ -146,8 +146,8 @@ struct Walker {
     int kstep;      // +1 moving up, -1 moving down
 };
 
-__device__ inline void walk_init(Walker &w, double base, double c, double h, double inv_h, int K,
-                                 double l0, bool bwd) {
+__device__ inline void walk_init(Walker &w, double base, double c, double ic, double h, double inv_h,
+                                 int K, double l0, bool bwd) {
     const bool up = (c > 0) != bwd;
     const double z0 = base + c * l0;
     int k = up ? (int)floor(z0 * inv_h) : (int)ceil(z0 * inv_h) - 1;
@@ -155,8 +155,8 @@ __device__ inline void walk_init(Walker &w, double base, double c, double h, dou
     w.k = k;
     w.kstep = up ? 1 : -1;
     w.mnext = up ? k + 1 : k;
-    w.hc = h / c;
-    w.bc = base / c;
+    w.hc = h * ic;
+    w.bc = base * ic;
     w.lcur = l0;
     w.lnp = w.mnext * w.hc - w.bc;
 }
@@ -193,14 +193,14 @@ struct Bound {
     double lz, zf, lside;
 };
 
-__device__ inline Bound boundary_of(double base, double c, double Lt, double H, int dir,
+__device__ inline Bound boundary_of(double base, double c, double ic, double Lt, double H, int dir,
                                     bool at_exit, int meta) {
     Bound b;
     const bool up = (c > 0) != (dir == 1);
     const bool top = at_exit ? up : !up;
     b.zf = top ? H : 0.0;
     b.face_z = top ? MOC_FACE_ZMAX : MOC_FACE_ZMIN;
-    b.lz = (b.zf - base) / c;
+    b.lz = (b.zf - base) * ic;
     const bool far_end = (dir == 0) == at_exit;     // the l = Lt end of the 2D track
     b.lside = far_end ? Lt : 0.0;
     b.face_s = far_end ? ((meta >> 20) & 0xf) : ((meta >> 16) & 0xf);
@@ -243,7 +243,7 @@ __device__ inline long long successor_slot(const SweepArgs &a, const Bound &b, l
     }
     const long long s2 = t2 * P + n2;
     const double c2 = a.cot[(a.t_meta[t2] & 0xffff) * P + n2];
-    const long long i2 = llrint((z2 - a.zeta[s2] - c2 * l2) / a.dz) - a.ilo[s2];
+    const long long i2 = llrint((z2 - a.zeta[s2] - c2 * l2) * a.inv_dz) - a.ilo[s2];
     if (i2 < 0 || i2 >= (long long)a.cnt[s2]) return -1;
     return 2 * (a.trk_off[s2] + i2) + d2;
 }
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
     const int n = (int)(s - t * P);
     const int meta = a.t_meta[t];
     const int an = (meta & 0xffff) * P + n;
-    const double c = a.cot[an], secl = a.secl[an], W = a.wgt[an];
+    const double c = a.cot[an], ic = a.icot[an], secl = a.secl[an], W = a.wgt[an];
     const double Lt = a.t_len[t];
     const int f0 = a.t_first[t], f1 = a.t_first[t + 1];
     const int tr = lane / C;
@@ -283,7 +283,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
     const bool active = (tr < a.T) && (zi < (long long)a.cnt[s]) && ng > 0;
     const double base = line_base(a, s, zi);
     double ls = 1e300, le = -1e300;
-    if (active) clip_line(base, c, Lt, a.H, ls, le);
+    if (active) clip_line(base, c, ic, Lt, a.H, ls, le);
     const double l_lo = wave_min(ls), l_hi = wave_max(le);
     const long long slot_in = 2 * (a.trk_off[s] + zi) + dir;
     const R *sigt = (const R *)a.sigt;
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
     for (int j = 0; j < kGL; ++j) psi[j] = 0;
     double s_in = 0.0;
     if (active && a.mode == 0) {
-        const bool from_vacuum = is_vacuum(a, boundary_of(base, c, Lt, a.H, dir, false, meta));
+        const bool from_vacuum = is_vacuum(a, boundary_of(base, c, ic, Lt, a.H, dir, false, meta));
 #pragma unroll
         for (int j = 0; j < kGL; ++j)
             if (j < ng) {
@@ -307,7 +307,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
     const int k_first = seg_search(a.seg_pos, f0, f1, l_lo);
     const int k_last = seg_search(a.seg_pos, f0, f1, l_hi);
     Walker wk;
-    if (active) walk_init(wk, base, c, a.h, a.inv_h, K, dir ? le : ls, dir == 1);
+    if (active) walk_init(wk, base, c, ic, a.h, a.inv_h, K, dir ? le : ls, dir == 1);
     const int nk = k_last - k_first + 1;
     for (int kk = 0; kk < nk; ++kk) {
         const int k = dir ? (k_last - kk) : (k_first + kk);
@@ -354,7 +354,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
                 if (a.psi_exit) a.psi_exit[hook + j] = (double)psi[j];
             }
         s_out = wpsi;
-        const Bound b = boundary_of(base, c, Lt, a.H, dir, true, meta);
+        const Bound b = boundary_of(base, c, ic, Lt, a.H, dir, true, meta);
         if (is_vacuum(a, b)) {
             leak = wpsi;
         } else if (a.psi_out) {
@@ -426,6 +426,9 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
     const SweepArgs &a = wa.s;
     const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6);
     const int G = a.G, K = a.K, P = a.P, T = a.T;
+    // line stride inside a bundle: lanes S lines (S dz) apart fall in different
+    // layers, so fewer lanes add to the same LDS tally entry at once
+    const int S = wa.lstride;
     // C1: all groups of a line in one lane (G <= kGL), the common case
     const int C = C1 ? 1 : a.C, GL = C1 ? a.G : a.GL;
     const int KG = K * G;
@@ -494,15 +497,15 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
             if (n < P && (fn < 0 || fn == n)) {
                 const long long s = t * P + n;
                 const int cs = a.cnt[s];
-                const double c = a.cot[az * P + n];
+                const double c = a.cot[az * P + n], ic = a.icot[az * P + n];
                 auto ls_lt = [&](int i) {
                     double l0, l1;
-                    clip_line(line_base(a, s, i), c, Lt, a.H, l0, l1);
+                    clip_line(line_base(a, s, i), c, ic, Lt, a.H, l0, l1);
                     return l0 < wb_;
                 };
                 auto le_gt = [&](int i) {
                     double l0, l1;
-                    clip_line(line_base(a, s, i), c, Lt, a.H, l0, l1);
+                    clip_line(line_base(a, s, i), c, ic, Lt, a.H, l0, l1);
                     return l1 > wa_;
                 };
                 int a0 = 0, a1 = cs;        // first true of the rising predicate
@@ -521,7 +524,14 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                     hi = min(hi, (int)fi0 + T - 1);
                 }
             }
-            const int nb = (hi >= lo) ? (hi - lo + T) / T : 0;
+            // bundles: blocks of S*T consecutive lines, each split into S
+            // bundles of every S-th line (S = 1: T consecutive lines)
+            int nb = 0;
+            if (hi >= lo) {
+                const int nl = hi - lo + 1, ST = S * T;
+                const int blocks = (nl + ST - 1) / ST;
+                nb = (blocks - 1) * S + min(S, nl - (blocks - 1) * ST);
+            }
             int sc = nb;
             for (int o = 1; o < 64; o <<= 1) {
                 const int v = __shfl_up(sc, o, 64);
@@ -540,14 +550,21 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
             n = uniform(n);
             const long long s = t * P + n;
             const int an = az * P + n;
-            const double c = a.cot[an], secl = a.secl[an], W = a.wgt[an];
-            const int i = uniform(r_lo[n] + (bnd - bpre[n]) * T) + tr;
-            const bool active = (tr < T) && (i <= r_hi[n]) && ng > 0;
+            const double c = a.cot[an], ic = a.icot[an], secl = a.secl[an], W = a.wgt[an];
+            const int bl = bnd - bpre[n];
+            const int i0 = uniform(r_lo[n] + (bl / S) * S * T + bl % S);
+            const int nact = uniform(min(T, (r_hi[n] - i0) / S + 1));    // lines in this bundle (>= 1)
+            const int i = i0 + S * tr;
+            const bool active = (tr < nact) && ng > 0;
             const double base = line_base(a, s, i);
             double ls = 1e300, le = -1e300;
-            if (active) clip_line(base, c, Lt, a.H, ls, le);
-            // segments of the window touched by the bundle
-            const double u_lo = fmax(wave_min(ls), wa_), u_hi = fmin(wave_max(le), wb_);
+            if (active) clip_line(base, c, ic, Lt, a.H, ls, le);
+            // segments of the window touched by the bundle: the extents of
+            // consecutive lines of one stack move monotonically with the line
+            // index, so the first and last line bound them
+            const int last = (nact - 1) * C;
+            const double u_lo = fmax(fmin(__shfl(ls, 0, 64), __shfl(ls, last, 64)), wa_);
+            const double u_hi = fmin(fmax(__shfl(le, 0, 64), __shfl(le, last, 64)), wb_);
             int ka = 0, kb = nsw - 1;
             {
                 int lo2 = 0, hi2 = nsw;
@@ -573,7 +590,7 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                         if (j < ng) psi[j] = (R)pin[j];
                 } else {
                     const bool from_vacuum =
-                        !a.psi_entry && is_vacuum(a, boundary_of(base, c, Lt, a.H, dir, false, meta));
+                        !a.psi_entry && is_vacuum(a, boundary_of(base, c, ic, Lt, a.H, dir, false, meta));
 #pragma unroll
                     for (int j = 0; j < kGL; ++j)
                         if (j < ng) {
@@ -584,7 +601,7 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                 }
             }
             Walker wk;
-            if (active) walk_init(wk, base, c, a.h, a.inv_h, K, dir ? fmin(le, wb_) : fmax(ls, wa_), dir == 1);
+            if (active) walk_init(wk, base, c, ic, a.h, a.inv_h, K, dir ? fmin(le, wb_) : fmax(ls, wa_), dir == 1);
             const int nk = kb - ka + 1;
             for (int q = 0; q < nk; ++q) {
                 const int kk = dir ? (kb - q) : (ka + q);
@@ -643,7 +660,7 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                             if (a.psi_exit) a.psi_exit[hook + j] = (double)psi[j];
                         }
                     s_out += wpsi;
-                    const Bound b = boundary_of(base, c, Lt, a.H, dir, true, meta);
+                    const Bound b = boundary_of(base, c, ic, Lt, a.H, dir, true, meta);
                     if (is_vacuum(a, b)) {
                         leak += wpsi;
                     } else if (a.psi_out) {
@@ -781,14 +798,14 @@ __global__ void k_trace(SweepArgs a, const long long *tracks, long long ntr, int
     const long long t = s / P;
     const int n = (int)(s - t * P);
     const int an = (a.t_meta[t] & 0xffff) * P + n;
-    const double c = a.cot[an], secl = a.secl[an];
+    const double c = a.cot[an], ic = a.icot[an], secl = a.secl[an];
     const double Lt = a.t_len[t];
     const int f0 = a.t_first[t], f1 = a.t_first[t + 1];
     const double base = line_base(a, s, trk - a.trk_off[s]);
     double ls, le;
-    clip_line(base, c, Lt, a.H, ls, le);
+    clip_line(base, c, ic, Lt, a.H, ls, le);
     Walker wk;
-    walk_init(wk, base, c, a.h, a.inv_h, K, ls, false);
+    walk_init(wk, base, c, ic, a.h, a.inv_h, K, ls, false);
     int m = 0;
     for (int k = seg_search(a.seg_pos, f0, f1, ls); k < f1; ++k) {
         const double s0 = a.seg_pos[k];
@@ -953,7 +970,8 @@ SweepArgs Solver::sweep_args(int fp64, int exp_mode) const {
     std::memset(&a, 0, sizeof(a));
     a.cot = ws_ptr<double>(ws, lay.off_cot);
     a.secl = ws_ptr<double>(ws, lay.off_secl);
-    a.seca = ws_ptr<double>(ws, lay.off_seca);
+    a.icot = ws_ptr<double>(ws, lay.off_icot);
+    a.inv_dz = 1.0 / info.dz;
     a.wgt = ws_ptr<double>(ws, lay.off_wgt);
     a.t_len = ws_ptr<double>(ws, lay.off_t_len);
     a.t_first = ws_ptr<int>(ws, lay.off_t_first);
@@ -1014,11 +1032,11 @@ int Solver::upload(const Plan &p) {
         return hipMemcpyAsync(ws + off, src, bytes, hipMemcpyHostToDevice, stream);
     };
     // host staging kept alive until the stream has consumed it
-    std::vector<double> secl(p.cot.size()), seca(p.cot.size());
+    std::vector<double> secl(p.cot.size()), icot(p.cot.size());
     for (size_t i = 0; i < p.cot.size(); ++i) {
         double c = p.cot[i];
-        secl[i] = std::sqrt(1.0 + c * c);
-        seca[i] = std::sqrt(1.0 + c * c) / std::fabs(c);
+        secl[i] = std::sqrt(1.0 + c * c);   // 3D length per unit 2D length
+        icot[i] = 1.0 / c;                  // cot is never 0 (k >= 1 in the polar correction)
     }
     std::vector<int> tfirst(p.n2d + 1), tmeta(p.n2d), tlink(2 * p.n2d);
     for (int64_t t = 0; t <= p.n2d; ++t) tfirst[t] = (int)p.seg_first[t];
@@ -1030,7 +1048,7 @@ int Solver::upload(const Plan &p) {
     std::vector<float> sigt32(p.sigt.begin(), p.sigt.end());
     HIPCHK(put(lay.off_cot, p.cot.data(), p.cot.size() * 8));
     HIPCHK(put(lay.off_secl, secl.data(), secl.size() * 8));
-    HIPCHK(put(lay.off_seca, seca.data(), seca.size() * 8));
+    HIPCHK(put(lay.off_icot, icot.data(), icot.size() * 8));
     HIPCHK(put(lay.off_wgt, p.wgt.data(), p.wgt.size() * 8));
     HIPCHK(put(lay.off_t_len, p.L.data(), p.n2d * 8));
     HIPCHK(put(lay.off_t_first, tfirst.data(), tfirst.size() * 4));
@@ -1052,6 +1070,7 @@ int Solver::upload(const Plan &p) {
     // segments), so the longest units start first
     sw32 = window_fit(p, false);
     sw64 = window_fit(p, true);
+    lstride = p.lstride;
     std::vector<std::pair<double, int>> est(p.n2d);
     for (int64_t t = 0; t < p.n2d; ++t) {
         double lines = 0;
@@ -1126,6 +1145,7 @@ void Solver::launch_sweep(SweepArgs a, bool fp64, const int *units, int n_units,
         wa.filt_n = filt_n;
         wa.filt_i0 = filt_i0;
         wa.Sw = sw;
+        wa.lstride = lstride;
         const unsigned nb = units ? (unsigned)n_units : (unsigned)(2 * info.n_2d_tracks);
         if (nb == 0) return;
         const size_t lds = win_lds_bytes(sw, K, info.n_groups, fp64 ? 8 : 4);
@@ -1196,6 +1216,7 @@ WinArgs Solver::win_args_for_next_iteration() const {
     wa.s.psi_out = ws + (odd ? lay.off_psi1 : lay.off_psi0);
     wa.work = ws_ptr<int>(ws, lay.off_work);
     wa.Sw = sw32;
+    wa.lstride = lstride;
     return wa;
 }
 

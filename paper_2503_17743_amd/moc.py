@@ -49,7 +49,7 @@ class PlanInfo(C.Structure):
                 ("n_stacks", C.c_longlong), ("n_3d_tracks", C.c_longlong),
                 ("n_chunks", C.c_longlong), ("n_groups", C.c_int), ("tracks_per_wave", C.c_int),
                 ("dz", C.c_double), ("workspace_bytes", C.c_size_t), ("psi_bytes", C.c_size_t),
-                ("workspace_bytes_fp64", C.c_size_t)]
+                ("workspace_bytes_fp64", C.c_size_t), ("line_stride", C.c_int)]
 
 
 class SolveOpts(C.Structure):
