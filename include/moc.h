@@ -111,7 +111,8 @@ typedef struct {
     size_t psi_bytes;          /* of which: the two boundary angular-flux buffers  */
     size_t workspace_bytes_fp64; /* bytes for FP64 boundary flux (needed by the    */
                                  /* FP64 sweep to keep full precision)             */
-    int line_stride;           /* lines between neighbouring lanes of a sweep bundle */
+    int line_stride;           /* most lines between neighbouring lanes of a sweep */
+                               /* bundle (lines per axial layer)                  */
 } moc_plan_info;
 
 /* Solve controls.  sweep_fp64 = 1 runs segment arithmetic and angular flux in

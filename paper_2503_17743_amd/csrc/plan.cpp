@@ -466,14 +466,9 @@ std::string Plan::build(const moc_geometry &g, const moc_tracking &t, const moc_
         }
     }
     T = 64 / group_chunks(G);
-    // line stride of the windowed sweep's bundles: lanes one layer apart
-    // (h/dz lines) when every stack has enough lines at any 2D position
-    // (about H/dz) to keep bundles of stride * T lines mostly full
-    {
-        const int per_layer = std::max(1, (int)std::floor(h / dz + 1e-9));
-        const int deep = (int)(H / dz / (4.0 * T));
-        lstride = std::max(1, std::min(per_layer, deep));
-    }
+    // largest line stride of the windowed sweep's bundles: the lines of one
+    // stack per axial layer at a fixed 2D position
+    lstride = std::max(1, (int)std::floor(h / dz + 1e-9));
     trk_off.assign(n_stacks + 1, 0);
     chunk_off.assign(n_stacks + 1, 0);
     for (int64_t s = 0; s < n_stacks; ++s) {

@@ -426,9 +426,8 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
     const SweepArgs &a = wa.s;
     const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6);
     const int G = a.G, K = a.K, P = a.P, T = a.T;
-    // line stride inside a bundle: lanes S lines (S dz) apart fall in different
-    // layers, so fewer lanes add to the same LDS tally entry at once
-    const int S = wa.lstride;
+    // most lines of one stack a bundle may skip (the lines per axial layer)
+    const int Smax = wa.lstride;
     // C1: all groups of a line in one lane (G <= kGL), the common case
     const int C = C1 ? 1 : a.C, GL = C1 ? a.G : a.GL;
     const int KG = K * G;
@@ -437,7 +436,8 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
     //       reduced source Sw*KG | Sigma_t Sw*G | region Sw]
     int *r_lo = (int *)smem;
     int *r_hi = r_lo + kMaxPolar;
-    int *bpre = r_hi + kMaxPolar;
+    int *r_st = r_hi + kMaxPolar;       // line stride of each stack's bundles
+    int *bpre = r_st + kMaxPolar;
     double *acc_l = (double *)(smem + kWinFixedLds);
     double *s_pos = acc_l + (size_t)Sw * KG;
     R *q_l = (R *)(s_pos + Sw + 1);
@@ -525,10 +525,15 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                 }
             }
             // bundles: blocks of S*T consecutive lines, each split into S
-            // bundles of every S-th line (S = 1: T consecutive lines)
-            int nb = 0;
+            // bundles of every S-th line.  Lanes S lines (S dz) apart fall in
+            // different layers, so fewer lanes of one instruction add to the
+            // same LDS tally entry.  S = ceil(lines / T), at most the lines
+            // per layer, keeps the bundle count of consecutive bundles.
+            int nb = 0, S = 1;
             if (hi >= lo) {
-                const int nl = hi - lo + 1, ST = S * T;
+                const int nl = hi - lo + 1;
+                S = min(Smax, (nl + T - 1) / T);
+                const int ST = S * T;
                 const int blocks = (nl + ST - 1) / ST;
                 nb = (blocks - 1) * S + min(S, nl - (blocks - 1) * ST);
             }
@@ -539,6 +544,7 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
             }
             r_lo[lane] = lo;
             r_hi[lane] = hi;
+            r_st[lane] = S;
             bpre[lane + 1] = sc;
             if (lane == 0) bpre[0] = 0;
         }
@@ -552,6 +558,7 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
             const int an = az * P + n;
             const double c = a.cot[an], ic = a.icot[an], secl = a.secl[an], W = a.wgt[an];
             const int bl = bnd - bpre[n];
+            const int S = uniform(r_st[n]);
             const int i0 = uniform(r_lo[n] + (bl / S) * S * T + bl % S);
             const int nact = uniform(min(T, (r_hi[n] - i0) / S + 1));    // lines in this bundle (>= 1)
             const int i = i0 + S * tr;

@@ -110,12 +110,13 @@ def test_small_lattice_fixed_iterations(moc, nthreads, fp64):
 
 @pytest.mark.parametrize("fp64", [False, True])
 def test_deep_stacks_strided_bundles(moc, nthreads, fp64):
-    """A tall, thin lattice (600 lines per stack at any 2D position) where the
-    sweep's bundles take every 2nd line; fixed iterations against the oracle."""
+    """A tall, thin lattice (600 lines per stack at any 2D position, 10 per
+    layer) where the sweep's bundles take every S-th line (S up to 10) in
+    several blocks; fixed iterations against the oracle."""
     prob = P.small_lattice(seed=12, n=2, height=60.0, n_layers=60, n_groups=2, n_azim=4,
                            n_polar=2, axial=0.1)
     plan, s = _solver(moc, prob)
-    assert plan.info["line_stride"] == 2
+    assert plan.info["line_stride"] == 10
     om = O.Model(prob, n_threads=nthreads)
     for iters in (1, 4):
         s.reset()
