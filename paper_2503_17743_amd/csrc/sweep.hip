@@ -36,7 +36,11 @@
 namespace moc {
 
 constexpr double kFourPi = 12.566370614359172953850573533118;
-constexpr size_t kWinLdsBudget = 64 * 1024;   // dynamic LDS per windowed-sweep workgroup
+// dynamic LDS per windowed-sweep workgroup: 64 KB, or up to 78 KB (still two
+// workgroups per CU) when 64 KB holds only a few 2D segments of all layers
+constexpr size_t kWinLdsBudget = 64 * 1024;
+constexpr size_t kWinLdsBudgetDeep = 78 * 1024;
+constexpr int kWinDeepBelow = 8;
 constexpr int kSlots = 64;        // spread of the scalar accumulators
 constexpr int kSlotStride = 16;   // doubles between slots (separate cache lines)
 
@@ -1184,8 +1188,11 @@ int window_fit(const Plan &p, bool fp64) {
     int max_seg = 1;
     for (int64_t t = 0; t < p.n2d; ++t)
         max_seg = std::max<int>(max_seg, (int)(p.seg_first[t + 1] - p.seg_first[t]));
+    const int rb = fp64 ? 8 : 4;
     int sw = 0;
-    while (sw < max_seg && win_lds_bytes(sw + 1, p.K, p.G, fp64 ? 8 : 4) <= kWinLdsBudget) ++sw;
+    while (sw < max_seg && win_lds_bytes(sw + 1, p.K, p.G, rb) <= kWinLdsBudget) ++sw;
+    if (sw < kWinDeepBelow)
+        while (sw < max_seg && win_lds_bytes(sw + 1, p.K, p.G, rb) <= kWinLdsBudgetDeep) ++sw;
     return sw;
 }
 
