@@ -264,6 +264,10 @@ MOC_API int moc_server_step(moc_server *srv, int *n_active, int *n_queued);
 MOC_API int moc_server_poll(moc_server *srv, unsigned long long ticket, moc_stats *stats,
                             double *flux_out, size_t n);
 
+/* Non-releasing status check: *done = 1 once the request has retired (its
+ * result waits for moc_server_poll), 0 while queued or running. */
+MOC_API int moc_server_query(const moc_server *srv, unsigned long long ticket, int *done);
+
 MOC_API const char *moc_last_error(void);
 
 #ifdef __cplusplus

@@ -463,6 +463,20 @@ int moc_server_step(moc_server *srv, int *n_active, int *n_queued) {
     return srv->s.step(n_active, n_queued);
 }
 
+int moc_server_query(const moc_server *srv, unsigned long long ticket, int *done) {
+    if (!srv || !done) {
+        set_error("NULL argument");
+        return MOC_EINVAL;
+    }
+    auto it = srv->s.all.find(ticket);
+    if (it == srv->s.all.end()) {
+        set_error("unknown ticket");
+        return MOC_EINVAL;
+    }
+    *done = it->second->state == moc::DONE ? 1 : 0;
+    return MOC_OK;
+}
+
 int moc_server_poll(moc_server *srv, unsigned long long ticket, moc_stats *stats,
                     double *flux_out, size_t n) {
     if (!srv) {

@@ -104,6 +104,7 @@ def lib():
         "moc_server_destroy": ([VP], None),
         "moc_server_arena_overhead": ([C.c_int, C.POINTER(C.c_size_t)], C.c_int),
         "moc_eval_attenuation": ([VP, C.c_longlong, C.c_int, VP], C.c_int),
+        "moc_server_query": ([VP, C.c_ulonglong, C.POINTER(C.c_int)], C.c_int),
         "moc_server_submit": ([VP, VP, VP, C.POINTER(SolveOpts), C.POINTER(C.c_ulonglong)], C.c_int),
         "moc_server_step": ([VP, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
         "moc_server_poll": ([VP, C.c_ulonglong, C.POINTER(Stats), VP, C.c_size_t], C.c_int),
@@ -335,10 +336,17 @@ class Server:
         _check(lib().moc_server_step(self._h, C.byref(na), C.byref(nq)))
         return na.value, nq.value
 
+    def done(self, ticket) -> bool:
+        d = C.c_int()
+        _check(lib().moc_server_query(self._h, C.c_ulonglong(ticket), C.byref(d)))
+        return bool(d.value)
+
     def poll(self, ticket):
         """None while queued or running; else (flux, stats) and the request is released."""
+        if not self.done(ticket):
+            return None
         shape = self._shape[ticket]
-        flux = np.zeros(shape)
+        flux = np.empty(shape)
         st = Stats()
         rc = lib().moc_server_poll(self._h, C.c_ulonglong(ticket), C.byref(st), _p(flux), flux.size)
         if rc == MOC_EBUSY:
