@@ -45,7 +45,7 @@ constexpr int kSlots = 64;        // spread of the scalar accumulators
 constexpr int kSlotStride = 16;   // doubles between slots (separate cache lines)
 
 // scalar accumulator layout inside the scalar block (doubles / u64)
-enum ScalarQ { Q_SIN = 0, Q_SOUT, Q_LEAK, Q_NSEG, Q_LINKERR, Q_BAL, Q_ABS, Q_SRC, Q_COUNT };
+enum ScalarQ { Q_SIN = 0, Q_SOUT, Q_LEAK, Q_NSEG, Q_LINKERR, Q_BAL, Q_ABS, Q_SRC, Q_RES, Q_COUNT };
 __host__ __device__ inline size_t slot_index(int q, int slot) {
     return 64 + ((size_t)q * kSlots + slot) * kSlotStride;
 }
@@ -593,9 +593,13 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
             R psi[kGL];
 #pragma unroll
             for (int j = 0; j < kGL; ++j) psi[j] = 0;
+            // the lane carries W * psi along its line: then W * delta_psi is
+            // what Eq. 3 yields directly, and the tally needs no multiply
+            const R Wr = (R)W;
             if (MODE == 0 && active) {
                 const B *pin = (const B *)a.psi_in + slot * G + g0;
                 if (!starts) {
+                    // carried from the previous window (already scaled by W)
 #pragma unroll
                     for (int j = 0; j < kGL; ++j)
                         if (j < ng) psi[j] = (R)pin[j];
@@ -608,6 +612,7 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                             if (a.psi_entry) psi[j] = (R)a.psi_entry[hook + j];
                             else if (!from_vacuum) psi[j] = (R)pin[j];
                             s_in += W * (double)psi[j];
+                            psi[j] *= Wr;
                         }
                 }
             }
@@ -648,10 +653,11 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
 #pragma unroll
                     for (int j = 0; j < kGL; ++j)
                         if (j < GL) {
-                            R d = (psi[j] - qv[j]) * one_minus_exp<R>(stv[j] * lr, EXPM);
+                            // d = W (psi - qhat) (1 - e^-tau)  (Eq. 3 on the scaled flux)
+                            R d = fma(-Wr, qv[j], psi[j]) * one_minus_exp<R>(stv[j] * lr, EXPM);
                             if (!C1 && j >= ng) d = (R)0;
-                            psi[j] -= d;                                           // Eq. 3
-                            __hip_atomic_fetch_add(&acc_l[li + (C1 ? j : min(j, ng - 1))], W * (double)d,
+                            psi[j] -= d;
+                            __hip_atomic_fetch_add(&acc_l[li + (C1 ? j : min(j, ng - 1))], (double)d,
                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                         }
                 });
@@ -663,11 +669,14 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                     for (int j = 0; j < kGL; ++j)
                         if (j < ng) pc[j] = (B)psi[j];
                 } else {
+                    // back to the angular flux itself at the line's end
+                    const R iW = (R)(1.0 / W);
                     double wpsi = 0.0;
 #pragma unroll
                     for (int j = 0; j < kGL; ++j)
                         if (j < ng) {
-                            wpsi += W * (double)psi[j];
+                            wpsi += (double)psi[j];
+                            psi[j] *= iW;
                             if (a.psi_exit) a.psi_exit[hook + j] = (double)psi[j];
                         }
                     s_out += wpsi;
@@ -880,17 +889,48 @@ __device__ inline void finalize_elem(const FsrArgs &a, long long i, int slot_see
         absb = v * (st - out) * ph;
         src = v * a.q[i];
     }
+    // block totals (4 waves) -> one set of atomics per block, spread over
+    // the slots; the residual is a max over the Q_RES slots (res >= 0, so
+    // the bit patterns order like the values)
     res = wave_max(res);
     bal = wave_sum(bal);
     absb = wave_sum(absb);
     src = wave_sum(src);
+    __shared__ double red[4][4];
+    const int wv = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
-        const int sl = (int)(((long long)slot_seed * 4 + (threadIdx.x >> 6)) % kSlots);
-        atomicMax((unsigned long long *)&a.scal[0], (unsigned long long)__double_as_longlong(res));
+        red[wv][0] = res;
+        red[wv][1] = bal;
+        red[wv][2] = absb;
+        red[wv][3] = src;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int w = 1; w < nw; ++w) {
+            res = fmax(res, red[w][0]);
+            bal += red[w][1];
+            absb += red[w][2];
+            src += red[w][3];
+        }
+        const int sl = slot_seed % kSlots;
+        atomicMax((unsigned long long *)&a.scal[slot_index(Q_RES, sl)],
+                  (unsigned long long)__double_as_longlong(res));
         unsafeAtomicAdd(&a.scal[slot_index(Q_BAL, sl)], bal);
         unsafeAtomicAdd(&a.scal[slot_index(Q_ABS, sl)], absb);
         unsafeAtomicAdd(&a.scal[slot_index(Q_SRC, sl)], src);
     }
+}
+
+// Residual of one problem: the max over its Q_RES slots
+__device__ inline double residual_of(const double *scal) {
+    double r = 0.0;
+    for (int sl = 0; sl < kSlots; ++sl) r = fmax(r, scal[slot_index(Q_RES, sl)]);
+    return r;
+}
+
+__global__ void k_residual(double *scal) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) scal[0] = residual_of(scal);
 }
 
 __global__ __launch_bounds__(256) void k_source(FsrArgs a) {
@@ -938,7 +978,7 @@ __global__ void k_clear_scal_multi(const FsrArgs *args, int words) {
 // Residual of every active problem into one compact array.
 __global__ void k_gather_residual(const FsrArgs *args, int n_slots, double *out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n_slots) out[i] = args[i].scal[0];
+    if (i < n_slots) out[i] = residual_of(args[i].scal);
 }
 
 __global__ void k_fill_u32(unsigned *p, unsigned v, size_t n) {
@@ -1283,6 +1323,7 @@ int Solver::iterate(int nit, const moc_solve_opts &o, bool time_sweep) {
         launch_sweep(a, o.sweep_fp64 != 0);
         if (time_sweep) HIPCHK(hipEventRecord(events[2 * it + 1], stream));
         k_finalize<<<fblocks, 256, 0, stream>>>(f);
+        k_residual<<<1, 64, 0, stream>>>(ws_ptr<double>(ws, lay.off_scal));
         HIPCHK(hipGetLastError());
     }
     if (time_sweep) {
