@@ -34,6 +34,23 @@
  * inside the box; lines that merely graze a box edge are not tracks */
 #define TRACK_EPS 1e-9
 
+/* Planted mistakes for the mutation tests of the pins (0: none).  Each one
+ * is a plausible slip in a formula; the pin tests must fail for every one.
+ *   1 reduced source without the 1/(4 pi)    4 linearised attenuation (tau)
+ *   2 scattering matrix transposed           5 estimator without 4 pi qhat
+ *   3 track weight without sin(theta)        6 volumes from one direction */
+#ifndef ORC_MUTATION
+#define ORC_MUTATION 0
+#endif
+/* 1 - e^{-tau} as the oracle evaluates it (Eq. 3) */
+static inline double orc_atten(double tau) {
+#if ORC_MUTATION == 4
+    return tau;
+#else
+    return -expm1(-tau);
+#endif
+}
+
 struct orc_model {
     /* problem */
     int nx, ny, ns, K, G, M, P, A, A2, A4, Rc;
@@ -398,6 +415,9 @@ static int build_quadrature(struct orc_model *m, const orc_problem *p) {
             double sint = 1.0 / sqrt(1.0 + c * c);
             double wpol = m->wp[n >= P / 2 ? n : P - 1 - n];
             /* solid-angle weight x perpendicular area per 3D track */
+#if ORC_MUTATION == 3
+            sint = 1.0;
+#endif
             m->wgt[a * P + n] = m->dphi[a] * wpol * m->deff[a] * m->dz * sint;
         }
     }
@@ -678,7 +698,7 @@ static int build_traced(struct orc_model *m) {
     for (long long tr = 0; tr < n3; ++tr) {
         double w = orc_track_weight(m, tr);
         for (long long k = m->seg_off[tr]; k < m->seg_off[tr + 1]; ++k)
-            m->vol[m->seg_fsr[k]] += 2.0 * w * m->seg_len[k] / (4.0 * ORC_PI);
+            m->vol[m->seg_fsr[k]] += (ORC_MUTATION == 6 ? 1.0 : 2.0) * w * m->seg_len[k] / (4.0 * ORC_PI);
     }
     m->traced = 1;
     return 0;
@@ -827,8 +847,12 @@ int orc_solve(const orc_model *m, const double *q, double tol, int max_iters,
             int mm = mat[j];
             for (int g = 0; g < G; ++g) {
                 double s = q[j * G + g];
+#if ORC_MUTATION == 2
+                for (int gp = 0; gp < G; ++gp) s += m->sigs[(mm * G + g) * G + gp] * phi[j * G + gp];
+#else
                 for (int gp = 0; gp < G; ++gp) s += m->sigs[(mm * G + gp) * G + g] * phi[j * G + gp];
-                qhat[j * G + g] = s / (FOURPI * m->sigt[mm * G + g]);
+#endif
+                qhat[j * G + g] = s / ((ORC_MUTATION == 1 ? 1.0 : FOURPI) * m->sigt[mm * G + g]);
             }
         }
         memset(acc_t, 0, sizeof(double) * (size_t)nth * NF * G);
@@ -858,7 +882,7 @@ int orc_solve(const orc_model *m, const double *q, double tol, int max_iters,
                     for (int g = 0; g < G; ++g) {
                         double st = m->sigt[mm * G + g];
                         /* Eq. 3: psi_out = psi_in e^{-st l} + qhat (1 - e^{-st l}) */
-                        double dpsi = (psi[g] - qhat[j * G + g]) * (-expm1(-st * l));
+                        double dpsi = (psi[g] - qhat[j * G + g]) * orc_atten(st * l);
                         acc[j * G + g] += w * dpsi;
                         psi[g] -= dpsi;
                     }
@@ -883,7 +907,7 @@ int orc_solve(const orc_model *m, const double *q, double tol, int max_iters,
                 bal_lhs += a;
                 double st = m->sigt[mm * G + g];
                 double v = m->vol[j];
-                double ph = FOURPI * qhat[j * G + g] + (v > 0 ? a / (st * v) : 0.0);
+                double ph = (ORC_MUTATION == 5 ? 0.0 : FOURPI) * qhat[j * G + g] + (v > 0 ? a / (st * v) : 0.0);
                 double old = phi[j * G + g];
                 double d = fabs(ph - old);
                 double rr = (ph != 0.0) ? d / fabs(ph) : (d == 0.0 ? 0.0 : 1.0);
@@ -941,7 +965,7 @@ int orc_sweep_sample(const orc_model *m, long long n_items, const long long *tra
             long long j = f[k];
             int mm = fsr_material(m, j);
             for (int g = 0; g < G; ++g) {
-                double dpsi = (psi[g] - qhat[j * G + g]) * (-expm1(-m->sigt[mm * G + g] * l[k]));
+                double dpsi = (psi[g] - qhat[j * G + g]) * orc_atten(m->sigt[mm * G + g] * l[k]);
                 acc[j * G + g] += w * dpsi;
                 psi[g] -= dpsi;
             }

@@ -14,17 +14,20 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
+# the mutation tests point this at an oracle built with a planted mistake
+_LIB_OVERRIDE = os.environ.get("MOC_ORACLE_LIB")
 
 
-def build(verbose=False) -> str:
-    """Compile the oracle with gcc (plain C11 + OpenMP)."""
+def build(verbose=False, path=LIB_PATH, mutation=0) -> str:
+    """Compile the oracle with gcc (plain C11 + OpenMP); mutation > 0 plants
+    one of the mistakes listed in oracle.c (mutation tests only)."""
     cmd = ["gcc", "-O3", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
-           "-o", LIB_PATH + ".tmp", os.path.join(HERE, "oracle.c"), "-lm"]
+           f"-DORC_MUTATION={int(mutation)}", "-o", path + ".tmp", os.path.join(HERE, "oracle.c"), "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(LIB_PATH + ".tmp", LIB_PATH)
-    return LIB_PATH
+    os.replace(path + ".tmp", path)
+    return path
 
 
 class _Problem(C.Structure):
@@ -56,9 +59,12 @@ def lib():
     global _lib
     if _lib is None:
         src = os.path.join(HERE, "oracle.c")
-        if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(src):
-            build()
-        L = C.CDLL(LIB_PATH)
+        if _LIB_OVERRIDE:
+            L = C.CDLL(_LIB_OVERRIDE)
+        else:
+            if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(src):
+                build()
+            L = C.CDLL(LIB_PATH)
         P = C.POINTER
         L.orc_gauss_legendre.argtypes = [C.c_int, P(C.c_double), P(C.c_double)]
         L.orc_build.argtypes = [P(_Problem), C.c_int, C.c_int, P(C.c_void_p)]
