@@ -424,16 +424,18 @@ __device__ inline double uniform_val(double v) {
 
 // MODE 0: transport sweep; MODE 1: volume tally (W l / 4 pi per FSR).
 // EXPM 0: stable 1 - e^-tau; EXPM 1: 1 - hardware exp (precision study).
-template <typename R, typename B, int MODE, int EXPM, bool BWD, bool C1>
+// GC > 0: the group count is the compile-time constant GC (with C1), so the
+// per-group loops are straight-line code; GC = 0: G from the arguments.
+template <typename R, typename B, int MODE, int EXPM, bool BWD, bool C1, int GC = 0>
 __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit,
                                            unsigned char *smem) {
     const SweepArgs &a = wa.s;
     const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6);
-    const int G = a.G, K = a.K, P = a.P, T = a.T;
+    const int G = GC > 0 ? GC : a.G, K = a.K, P = a.P, T = a.T;
     // most lines of one stack a bundle may skip (the lines per axial layer)
     const int Smax = wa.lstride;
     // C1: all groups of a line in one lane (G <= kGL), the common case
-    const int C = C1 ? 1 : a.C, GL = C1 ? a.G : a.GL;
+    const int C = C1 ? 1 : a.C, GL = C1 ? G : a.GL;
     const int KG = K * G;
     const int Sw = wa.Sw;
     // LDS: [line ranges | FP64 tally Sw*KG | segment starts Sw+1 |
@@ -618,6 +620,20 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
             }
             Walker wk;
             if (active) walk_init(wk, base, c, ic, a.h, a.inv_h, K, dir ? fmin(le, wb_) : fmax(ls, wa_), dir == 1);
+            // a piece's tally atomics are issued after the next piece's reduced
+            // source loads, so those loads do not wait behind them (LDS
+            // operations of a wave complete in order)
+            R pend[kGL];
+            int pend_li = -1;
+            auto flush_pending = [&]() {
+                if (MODE == 0 && pend_li >= 0) {
+#pragma unroll
+                    for (int j = 0; j < kGL; ++j)
+                        if (j < GL)
+                            __hip_atomic_fetch_add(&acc_l[pend_li + (C1 ? j : min(j, ng - 1))], (double)pend[j],
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+            };
             const int nk = kb - ka + 1;
             for (int q = 0; q < nk; ++q) {
                 const int kk = dir ? (kb - q) : (ka + q);
@@ -650,6 +666,7 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
 #pragma unroll
                     for (int j = 0; j < kGL; ++j)
                         if (j < GL) qv[j] = q_l[li + (C1 ? j : min(j, ng - 1))];
+                    flush_pending();
 #pragma unroll
                     for (int j = 0; j < kGL; ++j)
                         if (j < GL) {
@@ -657,11 +674,12 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                             R d = fma(-Wr, qv[j], psi[j]) * one_minus_exp<R>(stv[j] * lr, EXPM);
                             if (!C1 && j >= ng) d = (R)0;
                             psi[j] -= d;
-                            __hip_atomic_fetch_add(&acc_l[li + (C1 ? j : min(j, ng - 1))], (double)d,
-                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                            pend[j] = d;
                         }
+                    pend_li = li;
                 });
             }
+            flush_pending();
             if (MODE == 0 && active) {
                 if (!ends) {
                     B *pc = (B *)a.psi_in + slot * G + g0;          // carried to the next window
@@ -732,13 +750,13 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
 
 // FP32 arithmetic: capped at 128 VGPRs so that two 512-thread workgroups
 // share a CU (4 waves per SIMD).  C1: G <= 8, all groups of a line in one lane.
-template <typename B, int MODE, int EXPM, bool C1>
+template <typename B, int MODE, int EXPM, bool C1, int GC = 0>
 __global__ __launch_bounds__(kWinThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_win(WinArgs wa) {
     extern __shared__ __align__(16) unsigned char smem[];
     // the direction is uniform per workgroup: specialise the whole unit on it
     const int code = wa.work[blockIdx.x];
-    if (code & 1) sweep_unit<float, B, MODE, EXPM, true, C1>(wa, code, blockIdx.x, smem);
-    else sweep_unit<float, B, MODE, EXPM, false, C1>(wa, code, blockIdx.x, smem);
+    if (code & 1) sweep_unit<float, B, MODE, EXPM, true, C1, GC>(wa, code, blockIdx.x, smem);
+    else sweep_unit<float, B, MODE, EXPM, false, C1, GC>(wa, code, blockIdx.x, smem);
 }
 
 // FP64 arithmetic (precision reference): no register cap
@@ -1174,7 +1192,18 @@ static void launch_win_c(const WinArgs &wa, unsigned nb, size_t lds, hipStream_t
     } else if (mode == 1) {
         k_sweep_win<B, 1, 0, C1><<<nb, kWinThreads, lds, st>>>(wa);
     } else if (expm == 0) {
-        k_sweep_win<B, 0, 0, C1><<<nb, kWinThreads, lds, st>>>(wa);
+        // the transport sweep with the group count compiled in (G <= 8)
+        switch (C1 ? wa.s.G : 0) {
+        case 1: k_sweep_win<B, 0, 0, true, 1><<<nb, kWinThreads, lds, st>>>(wa); break;
+        case 2: k_sweep_win<B, 0, 0, true, 2><<<nb, kWinThreads, lds, st>>>(wa); break;
+        case 3: k_sweep_win<B, 0, 0, true, 3><<<nb, kWinThreads, lds, st>>>(wa); break;
+        case 4: k_sweep_win<B, 0, 0, true, 4><<<nb, kWinThreads, lds, st>>>(wa); break;
+        case 5: k_sweep_win<B, 0, 0, true, 5><<<nb, kWinThreads, lds, st>>>(wa); break;
+        case 6: k_sweep_win<B, 0, 0, true, 6><<<nb, kWinThreads, lds, st>>>(wa); break;
+        case 7: k_sweep_win<B, 0, 0, true, 7><<<nb, kWinThreads, lds, st>>>(wa); break;
+        case 8: k_sweep_win<B, 0, 0, true, 8><<<nb, kWinThreads, lds, st>>>(wa); break;
+        default: k_sweep_win<B, 0, 0, C1><<<nb, kWinThreads, lds, st>>>(wa); break;
+        }
     } else {
         k_sweep_win<B, 0, 1, C1><<<nb, kWinThreads, lds, st>>>(wa);
     }
