@@ -783,8 +783,30 @@ __global__ __launch_bounds__(kWinThreads) __attribute__((amdgpu_waves_per_eu(4))
     // descriptors are never written during the launch (restrict): their
     // fields load once instead of after every store to the tallies
     const WinArgs &wa = descs[slot];
-    if (code & 1) sweep_unit<float, float, 0, 0, true, C1>(wa, code, blockIdx.x, smem);
-    else sweep_unit<float, float, 0, 0, false, C1>(wa, code, blockIdx.x, smem);
+    // units of one problem are contiguous in the work list, so neighbouring
+    // workgroups mostly run the same specialisation
+    if (C1) {
+        switch (wa.s.G) {
+#define MOC_MULTI_CASE(g)                                                                  \
+    case g:                                                                                \
+        if (code & 1) sweep_unit<float, float, 0, 0, true, true, g>(wa, code, blockIdx.x, smem);  \
+        else sweep_unit<float, float, 0, 0, false, true, g>(wa, code, blockIdx.x, smem);          \
+        break;
+            MOC_MULTI_CASE(1)
+            MOC_MULTI_CASE(2)
+            MOC_MULTI_CASE(3)
+            MOC_MULTI_CASE(4)
+            MOC_MULTI_CASE(5)
+            MOC_MULTI_CASE(6)
+            MOC_MULTI_CASE(7)
+            MOC_MULTI_CASE(8)
+#undef MOC_MULTI_CASE
+        default: break;
+        }
+    } else {
+        if (code & 1) sweep_unit<float, float, 0, 0, true, false>(wa, code, blockIdx.x, smem);
+        else sweep_unit<float, float, 0, 0, false, false>(wa, code, blockIdx.x, smem);
+    }
 }
 
 // ------------------------------------------------------------------ F(tau) hook
