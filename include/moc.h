@@ -264,6 +264,14 @@ MOC_API int moc_server_step(moc_server *srv, int *n_active, int *n_queued);
 MOC_API int moc_server_poll(moc_server *srv, unsigned long long ticket, moc_stats *stats,
                             double *flux_out, size_t n);
 
+/* Admission policy: with max_units > 0, queued requests are admitted in
+ * arrival order only while the active requests hold at most max_units work
+ * units (two per 2D track of each request; a request above the limit runs
+ * alone).  Large requests then run close to first-come-first-served and small
+ * ones share the GPU.  Default: 64 units per compute unit of the device;
+ * 0: admit whatever fits the arena. */
+MOC_API int moc_server_set_fill(moc_server *srv, long long max_units);
+
 /* Non-releasing status check: *done = 1 once the request has retired (its
  * result waits for moc_server_poll), 0 while queued or running. */
 MOC_API int moc_server_query(const moc_server *srv, unsigned long long ticket, int *done);

@@ -97,6 +97,7 @@ struct Server {
     size_t arena_bytes = 0;
     size_t usable_bytes = 0;    // arena bytes after the server tables
     int max_slots = 1;
+    long long fill_units = 0;   // admission stops at this many active work units (0: no limit)
     hipStream_t stream = nullptr;
     Arena alloc;
     unsigned long long next_ticket = 1;
@@ -148,6 +149,9 @@ int Server::admit() {
     for (auto it = queue.begin(); it != queue.end();) {
         Request *r = *it;
         if ((int)active.size() >= max_slots) break;
+        // fill target: keep arrival order and stop once the batch holds enough
+        // work to fill the GPU (a request larger than the target runs alone)
+        if (fill_units > 0 && !active.empty() && units + r->units > fill_units) break;
         size_t off = 0;
         const bool fits = (units + r->units <= (long long)kUnitCap) && alloc.alloc(r->bytes, off);
         if (!fits) {
@@ -365,6 +369,14 @@ int moc_server_create(void *dev_arena, size_t arena_bytes, int max_slots, void *
     moc::Server &s = sv->s;
     s.arena = static_cast<char *>(dev_arena);
     s.arena_bytes = arena_bytes;
+    {
+        // default fill target: 64 work units per compute unit (two resident
+        // sweep workgroups per CU, 32 rounds of them)
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            s.fill_units = 64LL * cus;
+    }
     s.max_slots = max_slots;
     s.stream = static_cast<hipStream_t>(stream);
     // device tables at the front of the arena
@@ -461,6 +473,15 @@ int moc_server_step(moc_server *srv, int *n_active, int *n_queued) {
         return MOC_EINVAL;
     }
     return srv->s.step(n_active, n_queued);
+}
+
+int moc_server_set_fill(moc_server *srv, long long max_units) {
+    if (!srv || max_units < 0) {
+        set_error("need a server and max_units >= 0");
+        return MOC_EINVAL;
+    }
+    srv->s.fill_units = max_units;
+    return MOC_OK;
 }
 
 int moc_server_query(const moc_server *srv, unsigned long long ticket, int *done) {

@@ -105,6 +105,7 @@ def lib():
         "moc_server_arena_overhead": ([C.c_int, C.POINTER(C.c_size_t)], C.c_int),
         "moc_eval_attenuation": ([VP, C.c_longlong, C.c_int, VP], C.c_int),
         "moc_server_query": ([VP, C.c_ulonglong, C.POINTER(C.c_int)], C.c_int),
+        "moc_server_set_fill": ([VP, C.c_longlong], C.c_int),
         "moc_server_submit": ([VP, VP, VP, C.POINTER(SolveOpts), C.POINTER(C.c_ulonglong)], C.c_int),
         "moc_server_step": ([VP, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
         "moc_server_poll": ([VP, C.c_ulonglong, C.POINTER(Stats), VP, C.c_size_t], C.c_int),
@@ -292,7 +293,7 @@ class Server:
     """Continuous-batching server on a device arena (torch uint8 tensor) and
     its own non-default stream (so the batched step can be graph-captured)."""
 
-    def __init__(self, arena_bytes, max_slots=64, device="cuda"):
+    def __init__(self, arena_bytes, max_slots=64, device="cuda", fill_units=None):
         import torch
         self.device = torch.device(device)
         self.stream = torch.cuda.Stream(self.device)
@@ -305,6 +306,8 @@ class Server:
                                        int(max_slots), VP(self.stream.cuda_stream), C.byref(h)))
         self._h = h
         self._shape = {}
+        if fill_units is not None:      # None: the library's default fill target
+            _check(lib().moc_server_set_fill(self._h, int(fill_units)))
 
     @staticmethod
     def overhead_bytes(max_slots=64) -> int:

@@ -48,10 +48,11 @@ def one_at_a_time(reqs, plans, tol, max_iters, use_arrivals=False):
                  "latency_s": lat.tolist(), "stats": stats}
 
 
-def run_stream(reqs, plans, tol, max_iters, arena_bytes, max_slots=64, use_arrivals=False):
+def run_stream(reqs, plans, tol, max_iters, arena_bytes, max_slots=64, use_arrivals=False,
+               fill_units=None):
     """Submit each request at its arrival time (all at t=0 unless use_arrivals)
     and step the server until every request is done."""
-    srv = moc.Server(arena_bytes, max_slots=max_slots)
+    srv = moc.Server(arena_bytes, max_slots=max_slots, fill_units=fill_units)
     n = len(reqs)
     arr = _arrivals(reqs, use_arrivals)
     tickets: Dict[int, int] = {}

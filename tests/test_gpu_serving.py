@@ -47,8 +47,8 @@ def _rel(a, b):
     return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300)))
 
 
-def _serve(moc, probs, arena_bytes, max_slots=64):
-    srv = moc.Server(arena_bytes, max_slots=max_slots)
+def _serve(moc, probs, arena_bytes, max_slots=64, fill_units=None):
+    srv = moc.Server(arena_bytes, max_slots=max_slots, fill_units=fill_units)
     plans = [moc.Plan(p) for p in probs]
     tickets = [srv.submit(pl, p.q, TOL, MAX_IT) for pl, p in zip(plans, probs)]
     results = {}
@@ -109,6 +109,18 @@ def test_slot_limit(moc):
     for p, (phi, st) in zip(probs, mixed):
         phi_a, _ = _alone(moc, p)
         assert _rel(phi, phi_a) < 1e-5
+
+
+def test_fill_target_admission(moc):
+    """With a fill target below one request's work, requests run one at a
+    time in arrival order; with a large one they all share the GPU."""
+    probs = [P.small_lattice(seed=60 + i, n=2, n_groups=2, n_layers=2, height=2.0) for i in range(4)]
+    one, max_one, _ = _serve(moc, probs, arena_bytes=1 << 30, fill_units=1)
+    assert max_one == 1
+    many, max_many, _ = _serve(moc, probs, arena_bytes=1 << 30, fill_units=0)
+    assert max_many == len(probs)
+    for (phi_a, _), (phi_b, _) in zip(one, many):
+        assert _rel(phi_a, phi_b) < 1e-12
 
 
 def test_server_rejects_invalid(moc):
