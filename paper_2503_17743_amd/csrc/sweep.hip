@@ -42,6 +42,7 @@ constexpr size_t kWinLdsBudget = 64 * 1024;
 constexpr size_t kWinLdsBudgetDeep = 78 * 1024;
 constexpr int kWinDeepBelow = 8;
 constexpr int kSlots = 64;        // spread of the scalar accumulators
+constexpr size_t kScalBytes = 128 * 1024;   // scalar block of a workspace
 constexpr int kSlotStride = 16;   // doubles between slots (separate cache lines)
 
 // scalar accumulator layout inside the scalar block (doubles / u64)
@@ -969,16 +970,31 @@ __device__ inline double residual_of(const double *scal) {
     return r;
 }
 
-__global__ void k_residual(double *scal) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) scal[0] = residual_of(scal);
-}
 
-__global__ __launch_bounds__(256) void k_source(FsrArgs a) {
+// Source update; also clears the scalar block (accumulators of this
+// iteration, the finalize ticket) before the sweep adds into it.
+__global__ __launch_bounds__(256) void k_source(FsrArgs a, int scal_words) {
+    unsigned *sw = (unsigned *)a.scal;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < scal_words; i += gridDim.x * blockDim.x)
+        sw[i] = 0u;
     source_elem(a, (long long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
+// Finalize; the last block to finish folds the residual slots into scal[0]
+// (a ticket counter in scal[1] orders it after every block's atomics).
 __global__ __launch_bounds__(256) void k_finalize(FsrArgs a) {
     finalize_elem(a, (long long)blockIdx.x * blockDim.x + threadIdx.x, blockIdx.x);
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned t = atomicAdd((unsigned *)&a.scal[1], 1u);
+        if (t == gridDim.x - 1) {
+            double r = 0.0;
+            for (int sl = 0; sl < kSlots; ++sl)
+                r = fmax(r, __hip_atomic_load(&a.scal[slot_index(Q_RES, sl)], __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT));
+            a.scal[0] = r;
+        }
+    }
 }
 
 // Batched forms: problem slot of a block from the block prefix blk_pre
@@ -1363,9 +1379,7 @@ int Solver::iterate(int nit, const moc_solve_opts &o, bool time_sweep) {
     }
     for (int it = 0; it < nit; ++it) {
         ++iter;
-        int rc = fill_zero(ws + lay.off_scal, 128 * 1024, stream);
-        if (rc) return rc;
-        k_source<<<fblocks, 256, 0, stream>>>(f);
+        k_source<<<fblocks, 256, 0, stream>>>(f, (int)(kScalBytes / 4));
         SweepArgs a = sweep_args(o.sweep_fp64, o.exp_mode);
         const bool odd = (iter % 2) == 1;
         a.psi_in = ws + (odd ? lay.off_psi0 : lay.off_psi1);
@@ -1374,7 +1388,6 @@ int Solver::iterate(int nit, const moc_solve_opts &o, bool time_sweep) {
         launch_sweep(a, o.sweep_fp64 != 0);
         if (time_sweep) HIPCHK(hipEventRecord(events[2 * it + 1], stream));
         k_finalize<<<fblocks, 256, 0, stream>>>(f);
-        k_residual<<<1, 64, 0, stream>>>(ws_ptr<double>(ws, lay.off_scal));
         HIPCHK(hipGetLastError());
     }
     if (time_sweep) {
