@@ -980,21 +980,10 @@ __global__ __launch_bounds__(256) void k_source(FsrArgs a, int scal_words) {
     source_elem(a, (long long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-// Finalize; the last block to finish folds the residual slots into scal[0]
-// (a ticket counter in scal[1] orders it after every block's atomics).
+// Finalize; the residual is the max over the Q_RES slots (folded by the
+// reader: the host, or the batched residual gather).
 __global__ __launch_bounds__(256) void k_finalize(FsrArgs a) {
     finalize_elem(a, (long long)blockIdx.x * blockDim.x + threadIdx.x, blockIdx.x);
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned t = atomicAdd((unsigned *)&a.scal[1], 1u);
-        if (t == gridDim.x - 1) {
-            double r = 0.0;
-            for (int sl = 0; sl < kSlots; ++sl)
-                r = fmax(r, __hip_atomic_load(&a.scal[slot_index(Q_RES, sl)], __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT));
-            a.scal[0] = r;
-        }
-    }
 }
 
 // Batched forms: problem slot of a block from the block prefix blk_pre
@@ -1425,7 +1414,9 @@ int Solver::read_stats(moc_stats *st) {
     };
     std::memset(st, 0, sizeof(*st));
     st->iters = iter;
-    st->residual = (iter <= 1) ? 1.0 : sc[0];
+    double rmax = 0.0;
+    for (int i = 0; i < kSlots; ++i) rmax = std::max(rmax, sc[slot_index(Q_RES, i)]);
+    st->residual = (iter <= 1) ? 1.0 : rmax;
     st->balance_lhs = sum(Q_BAL);
     st->balance_rhs = sum(Q_SIN) - sum(Q_SOUT);
     st->absorption = sum(Q_ABS);
@@ -1442,9 +1433,14 @@ int Solver::read_stats(moc_stats *st) {
 }
 
 int Solver::read_residual(double *r) {
-    HIPCHK(hipMemcpyAsync(r, ws + lay.off_scal, 8, hipMemcpyDeviceToHost, stream));
+    // the Q_RES slots are one contiguous run of kSlots * kSlotStride doubles
+    std::vector<double> sl((size_t)kSlots * kSlotStride);
+    HIPCHK(hipMemcpyAsync(sl.data(), ws + lay.off_scal + slot_index(Q_RES, 0) * 8, sl.size() * 8,
+                          hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
-    if (iter <= 1) *r = 1.0;
+    double m = 0.0;
+    for (int i = 0; i < kSlots; ++i) m = std::max(m, sl[(size_t)i * kSlotStride]);
+    *r = (iter <= 1) ? 1.0 : m;
     return MOC_OK;
 }
 
