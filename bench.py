@@ -70,54 +70,6 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def max_rel(a, b):
-    import numpy as np
-    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300)))
-
-
-def serving_bench(n_requests, arena_gib, tol=1e-6, max_iters=400, load=0.8, radial=0.05,
-                  axial=0.2, poisson=True):
-    """Continuous batching against one-at-a-time on the same requests: first
-    all arriving at once (throughput), then Poisson arrivals at `load` times
-    the one-at-a-time service rate (latency)."""
-    from paper_2503_17743_amd import moc, problems as P, serve as S
-    probs = [r.problem for r in P.serving_stream(n_requests=n_requests, radial=radial, axial=axial)]
-    reqs = P.with_arrivals(probs, None)
-    plans = S.plan_requests(reqs)
-    arena = moc.Server.overhead_bytes(64) + int(arena_gib * (1 << 30))
-    tag = f"{n_requests} requests at {radial}/{axial} cm"
-    log(f"serving ({tag}): one at a time ...")
-    phi_seq, seq = S.one_at_a_time(reqs, plans, tol, max_iters)
-    log(f"serving ({tag}): one at a time {seq['wall_s']:.2f} s; batched ...")
-    phi_bat, bat = S.run_stream(reqs, plans, tol, max_iters, arena)
-    log(f"serving ({tag}): batched {bat['wall_s']:.2f} s")
-    err = max(max_rel(a, b) for a, b in zip(phi_bat, phi_seq))
-    conv = all(st["converged"] for st in bat["stats"]) and all(st["converged"] for st in seq["stats"])
-    out = {
-        "workload": (f"{n_requests} independent fixed-source lattice solves to residual {tol:g} "
-                     f"(4x4/8x8/16x16 cells, 10-50 layers, 1-7 groups, 8-32 azimuthal x 2-6 "
-                     f"polar, {radial}/{axial} cm spacing)"),
-        "arena_bytes": arena,
-        "all_converged": conv,
-        "max_rel_diff_batched_vs_alone": err,
-        "offline": {"batched": S.summarize(bat, n_requests),
-                    "one_at_a_time": S.summarize(seq, n_requests),
-                    "throughput_ratio": seq["wall_s"] / bat["wall_s"]},
-    }
-    if poisson:
-        rate = load * n_requests / seq["wall_s"]
-        preqs = P.with_arrivals(probs, rate)
-        log(f"serving ({tag}): Poisson arrivals at {rate:.1f}/s, one at a time ...")
-        _, pseq = S.one_at_a_time(preqs, plans, tol, max_iters, use_arrivals=True)
-        log(f"serving ({tag}): Poisson one at a time {pseq['wall_s']:.2f} s; batched ...")
-        _, pbat = S.run_stream(preqs, plans, tol, max_iters, arena, use_arrivals=True)
-        log(f"serving ({tag}): Poisson batched {pbat['wall_s']:.2f} s")
-        out["poisson"] = {"rate_req_per_s": rate,
-                          "batched": S.summarize(pbat, n_requests),
-                          "one_at_a_time": S.summarize(pseq, n_requests)}
-    return out
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,7 +91,7 @@ def main():
 
     import numpy as np
     import torch
-    from paper_2503_17743_amd import moc, problems as P
+    from paper_2503_17743_amd import moc, problems as P, serve as S
 
     prob = P.get(args.workload)
     torch.cuda.set_device(0)
@@ -185,10 +137,10 @@ def main():
     solver.close()
     serving = None
     if args.serving_requests > 0:
-        serving = serving_bench(args.serving_requests, args.serving_arena_gib)
+        serving = S.compare(args.serving_requests, args.serving_arena_gib, log=log)
         # smaller requests (coarser tracking): per-iteration overheads matter more
-        serving["small_requests"] = serving_bench(2 * args.serving_requests, args.serving_arena_gib,
-                                                  radial=0.2, axial=0.5, poisson=False)
+        serving["small_requests"] = S.compare(2 * args.serving_requests, args.serving_arena_gib,
+                                              radial=0.2, axial=0.5, poisson=False, log=log)
     line = {
         "metric": "segment-group integrations/s at 1e-5 vs FP64",
         "value": value,

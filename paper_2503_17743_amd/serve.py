@@ -5,12 +5,17 @@ arrival time; throughput = requests (and segment-group updates) per second of
 wall time."""
 from __future__ import annotations
 
+import sys
 import time
 from typing import Dict, List
 
 import numpy as np
 
 from . import moc, problems as P
+
+
+def _stderr(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
 def plan_requests(reqs: List[P.Request]):
@@ -21,9 +26,15 @@ def _arrivals(reqs, use_arrivals):
     return np.array([r.arrival_s for r in reqs]) if use_arrivals else np.zeros(len(reqs))
 
 
-def one_at_a_time(reqs, plans, tol, max_iters, use_arrivals=False):
+def _progress(log, every, k, n, what):
+    if log is not None and every and (k % every == 0 or k == n):
+        log(f"{what}: {k}/{n} requests done")
+
+
+def one_at_a_time(reqs, plans, tol, max_iters, use_arrivals=False, log=None, log_every=0):
     """FIFO, one request on the GPU at a time: wait for its arrival, bind a
-    solver, solve to tol, read the flux back, release the workspace."""
+    solver, solve to tol, read the flux back, release the workspace.
+    `log(msg)` is called every `log_every` completed requests (0: never)."""
     import torch
     arr = _arrivals(reqs, use_arrivals)
     out, stats = [], []
@@ -43,15 +54,17 @@ def one_at_a_time(reqs, plans, tol, max_iters, use_arrivals=False):
         segg += st["seg_group_updates"] * st["iters"]
         out.append(phi)
         stats.append(st)
+        _progress(log, log_every, i + 1, len(reqs), "one at a time")
     torch.cuda.synchronize()
     return out, {"wall_s": time.perf_counter() - t0, "seg_group_updates": segg,
                  "latency_s": lat.tolist(), "stats": stats}
 
 
 def run_stream(reqs, plans, tol, max_iters, arena_bytes, max_slots=64, use_arrivals=False,
-               fill_units=None):
+               fill_units=None, log=None, log_every=0):
     """Submit each request at its arrival time (all at t=0 unless use_arrivals)
-    and step the server until every request is done."""
+    and step the server until every request is done (progress as for
+    one_at_a_time)."""
     srv = moc.Server(arena_bytes, max_slots=max_slots, fill_units=fill_units)
     n = len(reqs)
     arr = _arrivals(reqs, use_arrivals)
@@ -83,6 +96,7 @@ def run_stream(reqs, plans, tol, max_iters, arena_bytes, max_slots=64, use_arriv
             done[i] = res
             lat[i] = now - arr[i]
             segg += res[1]["seg_group_updates"] * res[1]["iters"]
+            _progress(log, log_every, len(done), n, "batched")
     wall = time.perf_counter() - t0
     srv.close()
     return [done[i][0] for i in range(n)], {
@@ -101,21 +115,82 @@ def summarize(d, n):
     return out
 
 
+def max_rel(a, b):
+    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300)))
+
+
+def compare(n_requests, arena_gib, tol=1e-6, max_iters=400, load=0.8, radial=0.05,
+            axial=0.2, poisson=True, log=None, log_every=0):
+    """Continuous batching against one-at-a-time on the same seeded requests:
+    first all arriving at once (throughput), then Poisson arrivals at `load`
+    times the one-at-a-time service rate (latency).  Returns a JSON-ready dict."""
+    def say(msg):
+        if log is not None:
+            log(msg)
+    probs = [r.problem for r in P.serving_stream(n_requests=n_requests, radial=radial, axial=axial)]
+    reqs = P.with_arrivals(probs, None)
+    t0 = time.perf_counter()
+    plans = plan_requests(reqs)
+    tag = f"{n_requests} requests at {radial}/{axial} cm"
+    say(f"serving ({tag}): planned in {time.perf_counter() - t0:.1f} s; one at a time ...")
+    arena = moc.Server.overhead_bytes(64) + int(arena_gib * (1 << 30))
+    kw = dict(log=log, log_every=log_every)
+    phi_seq, seq = one_at_a_time(reqs, plans, tol, max_iters, **kw)
+    say(f"serving ({tag}): one at a time {seq['wall_s']:.2f} s; batched ...")
+    phi_bat, bat = run_stream(reqs, plans, tol, max_iters, arena, **kw)
+    say(f"serving ({tag}): batched {bat['wall_s']:.2f} s")
+    err = max(max_rel(a, b) for a, b in zip(phi_bat, phi_seq))
+    conv = all(st["converged"] for st in bat["stats"]) and all(st["converged"] for st in seq["stats"])
+    out = {
+        "workload": (f"{n_requests} independent fixed-source lattice solves to residual {tol:g} "
+                     f"(4x4/8x8/16x16 cells, 10-50 layers, 1-7 groups, 8-32 azimuthal x 2-6 "
+                     f"polar, {radial}/{axial} cm spacing)"),
+        "arena_bytes": arena,
+        "all_converged": conv,
+        "max_rel_diff_batched_vs_alone": err,
+        "offline": {"batched": summarize(bat, n_requests),
+                    "one_at_a_time": summarize(seq, n_requests),
+                    "throughput_ratio": seq["wall_s"] / bat["wall_s"]},
+    }
+    if poisson:
+        rate = load * n_requests / seq["wall_s"]
+        preqs = P.with_arrivals(probs, rate)
+        say(f"serving ({tag}): Poisson arrivals at {rate:.1f}/s, one at a time ...")
+        _, pseq = one_at_a_time(preqs, plans, tol, max_iters, use_arrivals=True, **kw)
+        say(f"serving ({tag}): Poisson one at a time {pseq['wall_s']:.2f} s; batched ...")
+        _, pbat = run_stream(preqs, plans, tol, max_iters, arena, use_arrivals=True, **kw)
+        say(f"serving ({tag}): Poisson batched {pbat['wall_s']:.2f} s")
+        out["poisson"] = {"rate_req_per_s": rate, "load": load,
+                          "batched": summarize(pbat, n_requests),
+                          "one_at_a_time": summarize(pseq, n_requests)}
+    return out
+
+
 def main(argv=None):
-    """Run a seeded request stream one way and print one JSON summary line:
-    python -m paper_2503_17743_amd.serve [--requests N] [--mode batched|one]"""
+    """Run a seeded request stream and print one JSON summary line:
+    python -m paper_2503_17743_amd.serve [--requests N] [--mode batched|one|compare]
+    `compare` runs both ways, all at t=0 and then under Poisson arrivals at
+    --load times the one-at-a-time rate; progress goes to stderr."""
     import argparse
     import json
     import torch
     ap = argparse.ArgumentParser()
     ap.add_argument("--requests", type=int, default=32)
-    ap.add_argument("--mode", choices=("batched", "one"), default="batched")
+    ap.add_argument("--mode", choices=("batched", "one", "compare"), default="batched")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--max-iters", type=int, default=400)
     ap.add_argument("--arena-gib", type=float, default=8.0)
     ap.add_argument("--rate", type=float, default=0.0, help="Poisson arrivals per s (0: all at t=0)")
+    ap.add_argument("--load", type=float, default=0.8, help="compare: Poisson load")
+    ap.add_argument("--radial", type=float, default=0.05)
+    ap.add_argument("--axial", type=float, default=0.2)
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
+    if args.mode == "compare":
+        out = compare(args.requests, args.arena_gib, args.tol, args.max_iters, args.load,
+                      args.radial, args.axial, log=_stderr, log_every=32)
+        print(json.dumps(out), flush=True)
+        return
     probs = [r.problem for r in P.serving_stream(n_requests=args.requests)]
     reqs = P.with_arrivals(probs, args.rate or None)
     plans = plan_requests(reqs)
