@@ -254,8 +254,13 @@ MOC_API int moc_server_submit(moc_server *srv, const moc_plan *plan, const doubl
 /* One step: admit waiting requests in arrival order while a slot is free
  * and the workspace fits (a request may be overtaken by smaller ones at most
  * 8 times), run one source iteration of every active request in one batched
- * launch sequence, and retire requests whose residual < tol or that reached
- * max_iters.  *n_active / *n_queued (optional) report the state afterwards. */
+ * launch sequence, and retire requests whose residual < tol (after the first
+ * iteration) or that reached max_iters, as moc_solve stops.  While the batch
+ * does not change, the next step is launched before this one's residuals are
+ * read (the device applies the stopping rule itself and skips stopped
+ * requests), so the call may return with one step still running on the
+ * stream; that step's results are accounted by the next call.
+ * *n_active / *n_queued (optional) report the state afterwards. */
 MOC_API int moc_server_step(moc_server *srv, int *n_active, int *n_queued);
 
 /* MOC_EBUSY while the request is queued or running.  Once it has retired:

@@ -15,6 +15,7 @@ struct SweepArgs {
     const int *cnt;                               // [n_stacks]
     const long long *trk_off, *chunk_off;         // [n_stacks+1]
     const void *sigt;                             // [M][G] float or double
+    const double *sigt64;                         // [M][G] double (always)
     const void *qhat;                             // [n_fsr][G] float or double
     double *acc;                                  // [n_fsr][G]
     void *psi_in;                                 // boundary buffer read this sweep
@@ -40,6 +41,16 @@ struct WinArgs {
     const long long *filt_i0; // test hook: only lines [i0, i0+T) of it
     int Sw;                   // 2D segments per window
     int lstride;              // line stride inside a bundle (1: consecutive lines)
+};
+
+// Per-problem control of a batched step: the stopping rule and the state the
+// step advances (completed iterations, done once stopped).
+struct SlotCtl {
+    double tol;
+    int max_iters;
+    int iters;
+    int done;
+    int pad_;
 };
 
 struct FsrArgs {

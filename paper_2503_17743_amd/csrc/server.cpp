@@ -54,6 +54,12 @@ struct Arena {
         }
         return false;
     }
+    bool can_alloc(size_t n) const {
+        n = align_up(n);
+        for (const auto &f : free_)
+            if (f.second >= n) return true;
+        return false;
+    }
     void release(size_t off, size_t n) {
         n = align_up(n);
         auto it = free_.emplace(off, n).first;
@@ -87,6 +93,7 @@ struct Request {
     double residual = 1.0;
     moc_stats stats{};
     bool converged = false;
+    bool stopped = false;              // met the stopping rule (retired at the next drain)
     int bypassed = 0;
 };
 
@@ -108,27 +115,40 @@ struct Server {
     WinArgs *d_win = nullptr;
     FsrArgs *d_fsr = nullptr;
     int *d_blk = nullptr, *d_uslot = nullptr, *d_ucode = nullptr;
+    SlotCtl *d_ctl = nullptr;
     double *d_res = nullptr;
-    // pinned host staging
+    // pinned host staging; residuals in two halves, one per step in flight
     WinArgs *h_win = nullptr;
     FsrArgs *h_fsr = nullptr;
+    SlotCtl *h_ctl = nullptr;
     double *h_res = nullptr;
-    // current batch
+    // current batch: two graphs of the same step, writing the two residual halves
     BatchStep batch{};
     bool dirty = true;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    hipEvent_t done_ev[2] = {nullptr, nullptr};
+    // steps in flight: the oldest one's half (-1: none) and the next half to use
+    int inflight = -1;
+    int next_half = 0;
 
     ~Server() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
+        for (int b = 0; b < 2; ++b) {
+            if (exec[b]) (void)hipGraphExecDestroy(exec[b]);
+            if (graph[b]) (void)hipGraphDestroy(graph[b]);
+            if (done_ev[b]) (void)hipEventDestroy(done_ev[b]);
+        }
         if (h_win) (void)hipHostFree(h_win);
         if (h_fsr) (void)hipHostFree(h_fsr);
+        if (h_ctl) (void)hipHostFree(h_ctl);
         if (h_res) (void)hipHostFree(h_res);
     }
 
     int admit();
+    bool admissible() const;
     int rebuild();
+    int launch(int half);
+    int collect(int half, bool *changed);
     int step(int *n_active, int *n_queued);
     void retire(Request *r);
 };
@@ -189,7 +209,22 @@ int Server::admit() {
     return MOC_OK;
 }
 
-// Work list, block prefix and graph of the current set of active requests.
+// Whether admit() would take a queued request now (the same checks, no
+// allocation).
+bool Server::admissible() const {
+    if (queue.empty() || (int)active.size() >= max_slots) return false;
+    long long units = 0;
+    for (const Request *r : active) units += r->units;
+    for (const Request *r : queue) {
+        if (fill_units > 0 && !active.empty() && units + r->units > fill_units) return false;
+        if (units + r->units <= (long long)kUnitCap && alloc.can_alloc(r->bytes)) return true;
+        if (r->bypassed >= kMaxBypass) return false;
+    }
+    return false;
+}
+
+// Work list, block prefix, descriptor tables and graphs of the current set of
+// active requests (called with no step in flight).
 int Server::rebuild() {
     const int n = (int)active.size();
     std::vector<int> blk(n + 1, 0);
@@ -230,7 +265,20 @@ int Server::rebuild() {
         SRV_HIPCHK(hipMemcpyAsync(d_ucode, uc2.data(), uc2.size() * 4, hipMemcpyHostToDevice, stream));
     }
     SRV_HIPCHK(hipMemcpyAsync(d_blk, blk.data(), (n + 1) * 4, hipMemcpyHostToDevice, stream));
-    for (int i = 0; i < n; ++i) h_fsr[i] = active[i]->solver.fsr_args();
+    // descriptors and FSR tables stay fixed while the batch does; each
+    // problem's iteration count (its boundary-buffer parity) and stopping
+    // state are kept on the device and advanced by the step itself
+    for (int i = 0; i < n; ++i) {
+        const Request *r = active[i];
+        h_win[i] = r->solver.win_args_batched();
+        h_fsr[i] = r->solver.fsr_args();
+        h_ctl[i] = SlotCtl{r->opts.tol, r->opts.max_iters, r->iters, 0, 0};
+    }
+    if (n > 0) {
+        SRV_HIPCHK(hipMemcpyAsync(d_win, h_win, n * sizeof(WinArgs), hipMemcpyHostToDevice, stream));
+        SRV_HIPCHK(hipMemcpyAsync(d_fsr, h_fsr, n * sizeof(FsrArgs), hipMemcpyHostToDevice, stream));
+        SRV_HIPCHK(hipMemcpyAsync(d_ctl, h_ctl, n * sizeof(SlotCtl), hipMemcpyHostToDevice, stream));
+    }
     SRV_HIPCHK(hipStreamSynchronize(stream));
     batch.win_table = d_win;
     batch.fsr_table = d_fsr;
@@ -238,35 +286,39 @@ int Server::rebuild() {
     batch.u_slot = d_uslot;
     batch.u_code = d_ucode;
     batch.res_dev = d_res;
+    batch.ctl = d_ctl;
     batch.n_slots = n;
     batch.n_units = (int)us2.size();
     batch.n_units_c1 = n_c1;
     batch.fsr_blocks = blk[n];
     batch.lds = lds;
-    if (exec) {
-        (void)hipGraphExecDestroy(exec);
-        exec = nullptr;
-    }
-    if (graph) {
-        (void)hipGraphDestroy(graph);
-        graph = nullptr;
+    for (int b = 0; b < 2; ++b) {
+        if (exec[b]) {
+            (void)hipGraphExecDestroy(exec[b]);
+            exec[b] = nullptr;
+        }
+        if (graph[b]) {
+            (void)hipGraphDestroy(graph[b]);
+            graph[b] = nullptr;
+        }
     }
     if (stream && n > 0) {
-        // one step = descriptor upload, batched iteration, residual download
-        SRV_HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e = hipMemcpyAsync(d_win, h_win, n * sizeof(WinArgs), hipMemcpyHostToDevice, stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(d_fsr, h_fsr, n * sizeof(FsrArgs), hipMemcpyHostToDevice, stream);
-        int rc = (e == hipSuccess) ? launch_batch_step(batch, stream) : MOC_EDEVICE;
-        if (!rc) e = hipMemcpyAsync(h_res, d_res, n * 8, hipMemcpyDeviceToHost, stream);
-        hipGraph_t g = nullptr;
-        hipError_t e2 = hipStreamEndCapture(stream, &g);
-        if (e != hipSuccess || rc || e2 != hipSuccess) {
-            if (g) (void)hipGraphDestroy(g);
-            set_error("graph capture of the batched step failed");
-            return MOC_EDEVICE;
+        // one step = batched iteration, residuals to one half of the pinned buffer
+        for (int b = 0; b < 2; ++b) {
+            SRV_HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+            const int rc = launch_batch_step(batch, stream);
+            hipError_t e = hipSuccess;
+            if (!rc) e = hipMemcpyAsync(h_res + (size_t)b * max_slots, d_res, n * 8, hipMemcpyDeviceToHost, stream);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(stream, &g);
+            if (e != hipSuccess || rc || e2 != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                set_error("graph capture of the batched step failed");
+                return MOC_EDEVICE;
+            }
+            graph[b] = g;
+            SRV_HIPCHK(hipGraphInstantiate(&exec[b], graph[b], nullptr, nullptr, 0));
         }
-        graph = g;
-        SRV_HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
     }
     dirty = false;
     return MOC_OK;
@@ -279,42 +331,88 @@ void Server::retire(Request *r) {
     r->state = DONE;
 }
 
-int Server::step(int *n_active, int *n_queued) {
-    int rc = admit();
-    if (rc) return rc;
-    if (dirty) {
-        rc = rebuild();
-        if (rc) return rc;
-    }
+// Launch one batched step whose residuals land in the given half.
+int Server::launch(int half) {
     const int n = (int)active.size();
-    if (n > 0) {
-        for (int i = 0; i < n; ++i) h_win[i] = active[i]->solver.win_args_for_next_iteration();
-        if (exec) {
-            SRV_HIPCHK(hipGraphLaunch(exec, stream));
-        } else {
-            SRV_HIPCHK(hipMemcpyAsync(d_win, h_win, n * sizeof(WinArgs), hipMemcpyHostToDevice, stream));
-            SRV_HIPCHK(hipMemcpyAsync(d_fsr, h_fsr, n * sizeof(FsrArgs), hipMemcpyHostToDevice, stream));
-            rc = launch_batch_step(batch, stream);
+    if (exec[half]) {
+        SRV_HIPCHK(hipGraphLaunch(exec[half], stream));
+    } else {
+        const int rc = launch_batch_step(batch, stream);
+        if (rc) return rc;
+        SRV_HIPCHK(hipMemcpyAsync(h_res + (size_t)half * max_slots, d_res, n * 8, hipMemcpyDeviceToHost, stream));
+    }
+    SRV_HIPCHK(hipEventRecord(done_ev[half], stream));
+    return MOC_OK;
+}
+
+// Wait for the step of one half and account it: every running problem has
+// done one more iteration.  The stopping rule is the device's (the same
+// inputs, so the same decision): an iteration after the first whose residual
+// is < tol, or max_iters.  A stopped problem is skipped by the steps still in
+// flight and retires at the next drain.
+int Server::collect(int half, bool *changed) {
+    SRV_HIPCHK(hipEventSynchronize(done_ev[half]));
+    const double *res = h_res + (size_t)half * max_slots;
+    for (size_t i = 0; i < active.size(); ++i) {
+        Request *r = active[i];
+        if (r->stopped) continue;
+        ++r->solver.iter;
+        ++r->iters;
+        r->residual = r->iters <= 1 ? 1.0 : res[i];
+        const bool conv = r->iters > 1 && r->residual < r->opts.tol;
+        if (conv || r->iters >= r->opts.max_iters) {
+            r->converged = conv;
+            r->stopped = true;
+            *changed = true;
+        }
+    }
+    return MOC_OK;
+}
+
+// One server step.  With nothing in flight: admit, rebuild if the batch
+// changed, launch.  Then the next step is launched before the current one is
+// read, so the GPU does not wait for the host between steps; problems that
+// stop are skipped by the device from then on, so running ahead changes no
+// result.  The pipeline drains (and stopped requests retire) when a problem
+// stops or a queued request could be admitted.
+int Server::step(int *n_active, int *n_queued) {
+    int rc = MOC_OK;
+    if (inflight < 0) {
+        rc = admit();
+        if (rc) return rc;
+        if (dirty) {
+            rc = rebuild();
             if (rc) return rc;
-            SRV_HIPCHK(hipMemcpyAsync(h_res, d_res, n * 8, hipMemcpyDeviceToHost, stream));
         }
-        SRV_HIPCHK(hipStreamSynchronize(stream));
-        std::vector<Request *> keep;
-        for (int i = 0; i < n; ++i) {
-            Request *r = active[i];
-            ++r->solver.iter;
-            ++r->iters;
-            r->residual = r->iters <= 1 ? 1.0 : h_res[i];
-            const bool conv = r->iters > 1 && r->residual < r->opts.tol;
-            if (conv || r->iters >= r->opts.max_iters) {
-                r->converged = conv;
-                retire(r);
-                dirty = true;
-            } else {
-                keep.push_back(r);
+        if (!active.empty()) {
+            rc = launch(next_half);
+            if (rc) return rc;
+            inflight = next_half;
+            next_half ^= 1;
+        }
+    }
+    if (inflight >= 0) {
+        rc = launch(next_half);
+        if (rc) return rc;
+        const int second = next_half;
+        next_half ^= 1;
+        bool changed = false;
+        rc = collect(inflight, &changed);
+        if (rc) return rc;
+        if (changed || admissible()) {
+            rc = collect(second, &changed);
+            if (rc) return rc;
+            inflight = -1;
+            std::vector<Request *> keep;
+            for (Request *r : active) {
+                if (r->stopped) retire(r);
+                else keep.push_back(r);
             }
+            if (keep.size() != active.size()) dirty = true;
+            active.swap(keep);
+        } else {
+            inflight = second;
         }
-        active.swap(keep);
     }
     if (n_active) *n_active = (int)active.size();
     if (n_queued) *n_queued = (int)queue.size();
@@ -334,7 +432,7 @@ extern "C" {
 static size_t server_table_bytes(int max_slots) {
     return moc::align_up(max_slots * sizeof(moc::WinArgs)) + moc::align_up(max_slots * sizeof(moc::FsrArgs)) +
            moc::align_up((max_slots + 1) * 4) + 2 * moc::align_up(moc::kUnitCap * 4) +
-           moc::align_up(max_slots * 8);
+           moc::align_up(max_slots * 8) + moc::align_up(max_slots * sizeof(moc::SlotCtl));
 }
 
 int moc_server_arena_overhead(int max_slots, size_t *bytes) {
@@ -392,6 +490,7 @@ int moc_server_create(void *dev_arena, size_t arena_bytes, int max_slots, void *
     const size_t o_us = take(moc::kUnitCap * 4);
     const size_t o_uc = take(moc::kUnitCap * 4);
     const size_t o_res = take(max_slots * 8);
+    const size_t o_ctl = take(max_slots * sizeof(moc::SlotCtl));
     if (off >= arena_bytes) {
         delete sv;
         set_error("arena too small for the server tables");
@@ -403,6 +502,7 @@ int moc_server_create(void *dev_arena, size_t arena_bytes, int max_slots, void *
     s.d_uslot = reinterpret_cast<int *>(s.arena + o_us);
     s.d_ucode = reinterpret_cast<int *>(s.arena + o_uc);
     s.d_res = reinterpret_cast<double *>(s.arena + o_res);
+    s.d_ctl = reinterpret_cast<moc::SlotCtl *>(s.arena + o_ctl);
     if (off != server_table_bytes(max_slots)) {
         delete sv;
         set_error("internal: server table size mismatch");
@@ -412,11 +512,18 @@ int moc_server_create(void *dev_arena, size_t arena_bytes, int max_slots, void *
     s.alloc.init(off, s.usable_bytes);
     if (hipHostMalloc((void **)&s.h_win, max_slots * sizeof(moc::WinArgs), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&s.h_fsr, max_slots * sizeof(moc::FsrArgs), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&s.h_res, max_slots * 8, hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void **)&s.h_ctl, max_slots * sizeof(moc::SlotCtl), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&s.h_res, 2 * max_slots * 8, hipHostMallocDefault) != hipSuccess) {
         delete sv;
         set_error("pinned host allocation failed");
         return MOC_ENOMEM;
     }
+    for (int b = 0; b < 2; ++b)
+        if (hipEventCreateWithFlags(&s.done_ev[b], hipEventDisableTiming) != hipSuccess) {
+            delete sv;
+            set_error("event creation failed");
+            return MOC_EDEVICE;
+        }
     *out = sv;
     return MOC_OK;
 }

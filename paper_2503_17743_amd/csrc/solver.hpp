@@ -13,6 +13,7 @@ namespace moc {
 struct SweepArgs;
 struct FsrArgs;
 struct WinArgs;
+struct SlotCtl;
 
 // One batched source iteration of several problems (serving): device tables
 // of per-problem descriptors and the work list of all their units.
@@ -22,6 +23,7 @@ struct BatchStep {
     const int *blk_pre;         // [n_slots+1] 256-thread blocks per problem (prefix)
     const int *u_slot, *u_code; // [n_units]
     double *res_dev;            // [n_slots] residual of each problem
+    SlotCtl *ctl;               // [n_slots] stopping rule and state of each problem (advanced by the step)
     int n_slots, n_units, fsr_blocks;
     int n_units_c1;             // units [0, n_units_c1) belong to problems with G <= 8
     size_t lds;                 // dynamic LDS of the batched sweep (max over problems)
@@ -64,7 +66,7 @@ struct Solver {
     void launch_sweep(SweepArgs a, bool fp64, const int *units = nullptr, int n_units = 0,
                       const int *filt_n = nullptr, const long long *filt_i0 = nullptr);
     int window_size(bool fp64) const { return fp64 ? sw64 : sw32; }
-    WinArgs win_args_for_next_iteration() const;
+    WinArgs win_args_batched() const;   // descriptor of the batched sweep (even orientation)
     size_t win_lds() const;
     int reset();
     int iterate(int nit, const moc_solve_opts &o, bool time_sweep);

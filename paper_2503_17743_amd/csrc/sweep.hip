@@ -53,20 +53,29 @@ __host__ __device__ inline size_t slot_index(int q, int slot) {
 
 // ------------------------------------------------------------------ helpers
 
-// F(tau) = 1 - e^{-tau} for tau >= 0 without cancellation: below tau = 1/2
-// F = tau p(tau), with p the degree-5 Chebyshev interpolant of (1 - e^-t)/t on
-// [0, 1/2] (max relative error of F 1.5 ulp in FP32); above it the hardware
-// exp2 is used, where 1 - e^-tau >= 0.39 limits the cancellation (about 3 ulp).
-__device__ inline float one_minus_exp_f32(float t) {
-    float p = -1.1237151e-3f;
-    p = fmaf(p, t, 8.1900032e-3f);
-    p = fmaf(p, t, -4.1630242e-2f);
-    p = fmaf(p, t, 1.6666245e-1f);
-    p = fmaf(p, t, -4.9999982e-1f);
-    p = fmaf(p, t, 1.0f);
-    const float large = 1.0f - __builtin_amdgcn_exp2f(t * -1.44269504088896341f);
-    return t < 0.5f ? t * p : large;
+constexpr float kLog2e = 1.44269504088896341f;
+// 1 - e^{-tau} switches form at tau = 1/2, i.e. at u = tau log2(e) below
+constexpr float kSmallU = 0.72134752044448170f;
+
+// F = 1 - 2^{-u} for u >= 0 without cancellation (the attenuation factor
+// 1 - e^{-tau} of Eq. 3 at u = tau log2(e)).  Below u = log2(e)/2 (tau = 1/2)
+// F = u p(u), with p the degree-5 interpolant of (1 - 2^-u)/u at the
+// Chebyshev nodes of [0, log2(e)/2]; above it the hardware exp2 is used,
+// where F >= 0.39 limits the cancellation.  Measured against FP64 over
+// tau in [2^-30, 40] with u = tau log2(e) rounded to FP32: within 2 ulp.
+__device__ inline float one_minus_exp2_f32(float u) {
+    float p = -1.2459162e-4f;
+    p = fmaf(p, u, 1.3103603e-3f);
+    p = fmaf(p, u, -9.6096816e-3f);
+    p = fmaf(p, u, 5.5502694e-2f);
+    p = fmaf(p, u, -2.4022642e-1f);
+    p = fmaf(p, u, 6.9314718e-1f);
+    const float large = 1.0f - __builtin_amdgcn_exp2f(-u);
+    return u < kSmallU ? u * p : large;
 }
+
+// F(tau) = 1 - e^{-tau} for tau >= 0 (the same evaluation, from tau itself)
+__device__ inline float one_minus_exp_f32(float t) { return one_minus_exp2_f32(t * kLog2e); }
 
 template <typename R>
 __device__ inline R one_minus_exp(R tau, int exp_mode);
@@ -404,11 +413,16 @@ constexpr int kWinWaves = kWinThreads / 64;
 constexpr int kMaxPolar = 64;
 constexpr size_t kWinFixedLds = 2048;   // per-stack line ranges and bundle prefix
 
-// Dynamic LDS of a window of Sw segments (see k_sweep_win for the layout).
+// Byte offset of the FP64 tally: after the reduced source, 8-byte aligned.
+__host__ __device__ inline size_t win_acc_offset(int Sw, int KG, int rbytes) {
+    return ((size_t)Sw * KG * rbytes + 7) & ~(size_t)7;
+}
+
+// Dynamic LDS of a window of Sw segments (layout in sweep_unit).
 __host__ __device__ inline size_t win_lds_bytes(int Sw, int K, int G, int rbytes) {
     const size_t kg = (size_t)K * G;
-    return kWinFixedLds + (size_t)Sw * kg * 8 + ((size_t)Sw + 1) * 8 + (size_t)Sw * kg * rbytes +
-           (size_t)Sw * G * rbytes + (size_t)Sw * 4 + 16;
+    return win_acc_offset(Sw, (int)kg, rbytes) + (size_t)Sw * kg * 8 + ((size_t)Sw + 1) * 8 +
+           (size_t)Sw * G * rbytes + (size_t)Sw * 4 + kWinFixedLds;
 }
 
 
@@ -429,8 +443,11 @@ __device__ inline double uniform_val(double v) {
 // per-group loops are straight-line code; GC = 0: G from the arguments.
 template <typename R, typename B, int MODE, int EXPM, bool BWD, bool C1, int GC = 0>
 __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit,
-                                           unsigned char *smem) {
+                                           unsigned char *smem, bool flip = false) {
     const SweepArgs &a = wa.s;
+    // boundary buffers of this sweep (flip: the descriptor's pair swapped)
+    void *const psi_in = flip ? a.psi_out : a.psi_in;
+    void *const psi_out = flip ? a.psi_in : a.psi_out;
     const int tid = threadIdx.x, lane = tid & 63, wave = uniform(tid >> 6);
     const int G = GC > 0 ? GC : a.G, K = a.K, P = a.P, T = a.T;
     // most lines of one stack a bundle may skip (the lines per axial layer)
@@ -439,17 +456,22 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
     const int C = C1 ? 1 : a.C, GL = C1 ? G : a.GL;
     const int KG = K * G;
     const int Sw = wa.Sw;
-    // LDS: [line ranges | FP64 tally Sw*KG | segment starts Sw+1 |
-    //       reduced source Sw*KG | Sigma_t Sw*G | region Sw]
-    int *r_lo = (int *)smem;
+    // LDS: [reduced source Sw*KG | FP64 tally Sw*KG | segment starts Sw+1 |
+    //       Sigma_t Sw*G | region Sw | line ranges].  The reduced source sits
+    // at offset 0, so a lane's per-group loads address it with immediate
+    // offsets from one register.
+    R *q_l = (R *)smem;
+    double *acc_l = (double *)(smem + win_acc_offset(Sw, KG, (int)sizeof(R)));
+    double *s_pos = acc_l + (size_t)Sw * KG;
+    R *s_st = (R *)(s_pos + Sw + 1);
+    int *s_reg = (int *)(s_st + (size_t)Sw * G);
+    int *r_lo = s_reg + Sw;
     int *r_hi = r_lo + kMaxPolar;
     int *r_st = r_hi + kMaxPolar;       // line stride of each stack's bundles
     int *bpre = r_st + kMaxPolar;
-    double *acc_l = (double *)(smem + kWinFixedLds);
-    double *s_pos = acc_l + (size_t)Sw * KG;
-    R *q_l = (R *)(s_pos + Sw + 1);
-    R *s_st = q_l + (size_t)Sw * KG;
-    int *s_reg = (int *)(s_st + (size_t)Sw * G);
+    // FP32 stable attenuation: Sigma_t is staged times log2(e), so that
+    // Sigma_t l is the exponent of 2 itself
+    constexpr bool kL2 = std::is_same<R, float>::value && EXPM == 0 && MODE == 0;
 
     const long long t = code >> 1;
     constexpr int dir = BWD ? 1 : 0;
@@ -488,7 +510,8 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
         if (MODE == 0) {
             for (int i = tid; i < nsw * G; i += kWinThreads) {
                 const int kk = i / G;
-                s_st[i] = sigt[a.reg_mat[a.seg_reg[k0 + kk]] * G + (i - kk * G)];
+                const int m = a.reg_mat[a.seg_reg[k0 + kk]] * G + (i - kk * G);
+                s_st[i] = kL2 ? (R)(a.sigt64[m] * 1.4426950408889634) : sigt[m];
             }
             for (int i = tid; i < nsw * KG; i += kWinThreads) {
                 const int kk = i / KG;
@@ -600,7 +623,7 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
             // what Eq. 3 yields directly, and the tally needs no multiply
             const R Wr = (R)W;
             if (MODE == 0 && active) {
-                const B *pin = (const B *)a.psi_in + slot * G + g0;
+                const B *pin = (const B *)psi_in + slot * G + g0;
                 if (!starts) {
                     // carried from the previous window (already scaled by W)
 #pragma unroll
@@ -660,7 +683,7 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                 for (int j = 0; j < kGL; ++j)
                     if (j < GL) stv[j] = C1 ? uniform_val(s_st[kk * G + j]) : s_st[kk * G + g0 + min(j, ng - 1)];
                 nseg += walk_segment<BWD>(wk, e, secl, K, [&](int kz, double l3, bool valid) {
-                    const int li = lb + kz * G;
+                    const int li = lb + (int)__umul24((unsigned)kz, (unsigned)G);
                     // a piece below kMinSeg adds nothing: F(0) = 0 keeps psi unchanged
                     const R lr = valid ? (R)l3 : (R)0;
                     R qv[kGL];
@@ -672,7 +695,9 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                     for (int j = 0; j < kGL; ++j)
                         if (j < GL) {
                             // d = W (psi - qhat) (1 - e^-tau)  (Eq. 3 on the scaled flux)
-                            R d = fma(-Wr, qv[j], psi[j]) * one_minus_exp<R>(stv[j] * lr, EXPM);
+                            const R f = kL2 ? (R)one_minus_exp2_f32((float)(stv[j] * lr))
+                                            : one_minus_exp<R>(stv[j] * lr, EXPM);
+                            R d = fma(-Wr, qv[j], psi[j]) * f;
                             if (!C1 && j >= ng) d = (R)0;
                             psi[j] -= d;
                             pend[j] = d;
@@ -683,7 +708,7 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
             flush_pending();
             if (MODE == 0 && active) {
                 if (!ends) {
-                    B *pc = (B *)a.psi_in + slot * G + g0;          // carried to the next window
+                    B *pc = (B *)psi_in + slot * G + g0;            // carried to the next window
 #pragma unroll
                     for (int j = 0; j < kGL; ++j)
                         if (j < ng) pc[j] = (B)psi[j];
@@ -702,10 +727,10 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                     const Bound b = boundary_of(base, c, ic, Lt, a.H, dir, true, meta);
                     if (is_vacuum(a, b)) {
                         leak += wpsi;
-                    } else if (a.psi_out) {
+                    } else if (psi_out) {
                         const long long slot2 = successor_slot(a, b, t, n, dir, base, c);
                         if (slot2 >= 0) {
-                            B *po = (B *)a.psi_out + slot2 * G + g0;
+                            B *po = (B *)psi_out + slot2 * G + g0;
 #pragma unroll
                             for (int j = 0; j < kGL; ++j)
                                 if (j < ng) po[j] = (B)psi[j];
@@ -777,10 +802,14 @@ __global__ __launch_bounds__(kWinThreads) void k_sweep_win_f64(WinArgs wa) {
 template <bool C1>
 __global__ __launch_bounds__(kWinThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_win_multi(
     const WinArgs *__restrict__ descs, const int *__restrict__ u_slot, const int *__restrict__ u_code,
-    int u0) {
+    const SlotCtl *__restrict__ ctl, int u0) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int slot = u_slot[u0 + blockIdx.x];
     const int code = u_code[u0 + blockIdx.x];
+    if (ctl[slot].done) return;      // stopped: a later step of the batch skips it
+    // a descriptor holds the boundary buffers of an even iteration count;
+    // problems with an odd count of completed iterations swap them
+    const bool flip = (ctl[slot].iters & 1) != 0;
     // descriptors are never written during the launch (restrict): their
     // fields load once instead of after every store to the tallies
     const WinArgs &wa = descs[slot];
@@ -790,8 +819,8 @@ __global__ __launch_bounds__(kWinThreads) __attribute__((amdgpu_waves_per_eu(4))
         switch (wa.s.G) {
 #define MOC_MULTI_CASE(g)                                                                  \
     case g:                                                                                \
-        if (code & 1) sweep_unit<float, float, 0, 0, true, true, g>(wa, code, blockIdx.x, smem);  \
-        else sweep_unit<float, float, 0, 0, false, true, g>(wa, code, blockIdx.x, smem);          \
+        if (code & 1) sweep_unit<float, float, 0, 0, true, true, g>(wa, code, blockIdx.x, smem, flip);  \
+        else sweep_unit<float, float, 0, 0, false, true, g>(wa, code, blockIdx.x, smem, flip);          \
         break;
             MOC_MULTI_CASE(1)
             MOC_MULTI_CASE(2)
@@ -805,8 +834,8 @@ __global__ __launch_bounds__(kWinThreads) __attribute__((amdgpu_waves_per_eu(4))
         default: break;
         }
     } else {
-        if (code & 1) sweep_unit<float, float, 0, 0, true, false>(wa, code, blockIdx.x, smem);
-        else sweep_unit<float, float, 0, 0, false, false>(wa, code, blockIdx.x, smem);
+        if (code & 1) sweep_unit<float, float, 0, 0, true, false>(wa, code, blockIdx.x, smem, flip);
+        else sweep_unit<float, float, 0, 0, false, false>(wa, code, blockIdx.x, smem, flip);
     }
 }
 
@@ -1000,30 +1029,44 @@ __device__ inline int slot_of_block(const int *blk_pre, int n_slots, int b) {
 
 __global__ __launch_bounds__(256) void k_source_multi(const FsrArgs *__restrict__ args,
                                                       const int *__restrict__ blk_pre,
-                                                      int n_slots) {
+                                                      const SlotCtl *__restrict__ ctl, int n_slots) {
     const int sl = slot_of_block(blk_pre, n_slots, blockIdx.x);
+    if (ctl[sl].done) return;
     source_elem(args[sl], (long long)(blockIdx.x - blk_pre[sl]) * blockDim.x + threadIdx.x);
 }
 
 __global__ __launch_bounds__(256) void k_finalize_multi(const FsrArgs *__restrict__ args,
                                                         const int *__restrict__ blk_pre,
-                                                        int n_slots) {
+                                                        const SlotCtl *__restrict__ ctl, int n_slots) {
     const int sl = slot_of_block(blk_pre, n_slots, blockIdx.x);
+    if (ctl[sl].done) return;
     const int b = blockIdx.x - blk_pre[sl];
     finalize_elem(args[sl], (long long)b * blockDim.x + threadIdx.x, b);
 }
 
-// Clear the scalar block of every active problem (blockIdx.y = slot).
-__global__ void k_clear_scal_multi(const FsrArgs *args, int words) {
+// Clear the scalar block of every running problem (blockIdx.y = slot); a
+// stopped one keeps its last iteration's totals.
+__global__ void k_clear_scal_multi(const FsrArgs *args, const SlotCtl *ctl, int words) {
+    if (ctl[blockIdx.y].done) return;
     unsigned *p = (unsigned *)args[blockIdx.y].scal;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < words; i += gridDim.x * blockDim.x)
         p[i] = 0u;
 }
 
-// Residual of every active problem into one compact array.
-__global__ void k_gather_residual(const FsrArgs *args, int n_slots, double *out) {
+// End of a batched step: the residual of every running problem into one
+// compact array, one more completed iteration, and the stopping rule (the
+// residual of an iteration after the first below tol, or max_iters reached).
+// A stopped problem is skipped by every later step of the batch, so steps
+// launched before the host has read this one leave its result as it is.
+__global__ void k_gather_residual(const FsrArgs *args, int n_slots, double *out, SlotCtl *ctl) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n_slots) out[i] = residual_of(args[i].scal);
+    if (i < n_slots && !ctl[i].done) {
+        const double r = residual_of(args[i].scal);
+        const int it = ctl[i].iters + 1;
+        out[i] = r;
+        ctl[i].iters = it;
+        if ((it > 1 && r < ctl[i].tol) || it >= ctl[i].max_iters) ctl[i].done = 1;
+    }
 }
 
 __global__ void k_fill_u32(unsigned *p, unsigned v, size_t n) {
@@ -1083,6 +1126,7 @@ SweepArgs Solver::sweep_args(int fp64, int exp_mode) const {
     a.chunk_off = ws_ptr<long long>(ws, lay.off_chunk_off);
     a.sigt = fp64 ? (const void *)ws_ptr<double>(ws, lay.off_sigt64)
                   : (const void *)ws_ptr<float>(ws, lay.off_sigt32);
+    a.sigt64 = ws_ptr<double>(ws, lay.off_sigt64);
     a.qhat = fp64 ? (const void *)ws_ptr<double>(ws, lay.off_qhat64)
                   : (const void *)ws_ptr<float>(ws, lay.off_qhat32);
     a.acc = ws_ptr<double>(ws, lay.off_acc);
@@ -1317,13 +1361,14 @@ int Solver::init(const Plan &p, char *workspace, size_t ws_bytes, hipStream_t st
     return rc;
 }
 
-WinArgs Solver::win_args_for_next_iteration() const {
+WinArgs Solver::win_args_batched() const {
     WinArgs wa;
     std::memset(&wa, 0, sizeof(wa));
     wa.s = sweep_args(0, 0);
-    const bool odd = ((iter + 1) % 2) == 1;
-    wa.s.psi_in = ws + (odd ? lay.off_psi0 : lay.off_psi1);
-    wa.s.psi_out = ws + (odd ? lay.off_psi1 : lay.off_psi0);
+    // buffers of an iteration that follows an even number of completed ones
+    // (the batched sweep swaps them after an odd number)
+    wa.s.psi_in = ws + lay.off_psi0;
+    wa.s.psi_out = ws + lay.off_psi1;
     wa.work = ws_ptr<int>(ws, lay.off_work);
     wa.Sw = sw32;
     wa.lstride = lstride;
@@ -1334,15 +1379,16 @@ size_t Solver::win_lds() const { return win_lds_bytes(sw32, K, info.n_groups, 4)
 
 int launch_batch_step(const BatchStep &b, hipStream_t st) {
     if (b.n_slots <= 0) return MOC_OK;
-    k_clear_scal_multi<<<dim3(8, b.n_slots), 256, 0, st>>>(b.fsr_table, 128 * 1024 / 4);
-    k_source_multi<<<b.fsr_blocks, 256, 0, st>>>(b.fsr_table, b.blk_pre, b.n_slots);
+    k_clear_scal_multi<<<dim3(8, b.n_slots), 256, 0, st>>>(b.fsr_table, b.ctl, 128 * 1024 / 4);
+    k_source_multi<<<b.fsr_blocks, 256, 0, st>>>(b.fsr_table, b.blk_pre, b.ctl, b.n_slots);
     if (b.n_units_c1 > 0)
-        k_sweep_win_multi<true><<<b.n_units_c1, kWinThreads, b.lds, st>>>(b.win_table, b.u_slot, b.u_code, 0);
+        k_sweep_win_multi<true><<<b.n_units_c1, kWinThreads, b.lds, st>>>(b.win_table, b.u_slot, b.u_code,
+                                                                            b.ctl, 0);
     if (b.n_units > b.n_units_c1)
         k_sweep_win_multi<false><<<b.n_units - b.n_units_c1, kWinThreads, b.lds, st>>>(
-            b.win_table, b.u_slot, b.u_code, b.n_units_c1);
-    k_finalize_multi<<<b.fsr_blocks, 256, 0, st>>>(b.fsr_table, b.blk_pre, b.n_slots);
-    k_gather_residual<<<(b.n_slots + 255) / 256, 256, 0, st>>>(b.fsr_table, b.n_slots, b.res_dev);
+            b.win_table, b.u_slot, b.u_code, b.ctl, b.n_units_c1);
+    k_finalize_multi<<<b.fsr_blocks, 256, 0, st>>>(b.fsr_table, b.blk_pre, b.ctl, b.n_slots);
+    k_gather_residual<<<(b.n_slots + 255) / 256, 256, 0, st>>>(b.fsr_table, b.n_slots, b.res_dev, b.ctl);
     HIPCHK(hipGetLastError());
     return MOC_OK;
 }

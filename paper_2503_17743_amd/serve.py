@@ -119,11 +119,27 @@ def max_rel(a, b):
     return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300)))
 
 
+def _pool(runs, n):
+    """Summary of repeated runs of one mode: mean wall time, pooled latencies."""
+    wall = float(np.mean([d["wall_s"] for d in runs]))
+    lat = np.concatenate([np.array(d["latency_s"]) for d in runs])
+    out = {"requests": n, "runs": len(runs), "wall_s": wall, "wall_s_each": [d["wall_s"] for d in runs],
+           "req_per_s": n / wall,
+           "seg_group_per_s": float(np.mean([d["seg_group_updates"] / d["wall_s"] for d in runs])),
+           "latency_p50_s": float(np.percentile(lat, 50)),
+           "latency_p99_s": float(np.percentile(lat, 99))}
+    if "max_active" in runs[0]:
+        out["max_active"] = max(d["max_active"] for d in runs)
+    return out
+
+
 def compare(n_requests, arena_gib, tol=1e-6, max_iters=400, load=0.8, radial=0.05,
-            axial=0.2, poisson=True, log=None, log_every=0):
+            axial=0.2, poisson=True, log=None, log_every=0, repeats=2):
     """Continuous batching against one-at-a-time on the same seeded requests:
-    first all arriving at once (throughput), then Poisson arrivals at `load`
-    times the one-at-a-time service rate (latency).  Returns a JSON-ready dict."""
+    first all arriving at once (throughput; with repeats=2 the runs go one,
+    batched, batched, one, so that neither mode always runs on a GPU that has
+    been busy longer), then Poisson arrivals at `load` times the one-at-a-time
+    service rate (latency).  Returns a JSON-ready dict."""
     def say(msg):
         if log is not None:
             log(msg)
@@ -132,15 +148,23 @@ def compare(n_requests, arena_gib, tol=1e-6, max_iters=400, load=0.8, radial=0.0
     t0 = time.perf_counter()
     plans = plan_requests(reqs)
     tag = f"{n_requests} requests at {radial}/{axial} cm"
-    say(f"serving ({tag}): planned in {time.perf_counter() - t0:.1f} s; one at a time ...")
+    say(f"serving ({tag}): planned in {time.perf_counter() - t0:.1f} s")
     arena = moc.Server.overhead_bytes(64) + int(arena_gib * (1 << 30))
     kw = dict(log=log, log_every=log_every)
-    phi_seq, seq = one_at_a_time(reqs, plans, tol, max_iters, **kw)
-    say(f"serving ({tag}): one at a time {seq['wall_s']:.2f} s; batched ...")
-    phi_bat, bat = run_stream(reqs, plans, tol, max_iters, arena, **kw)
-    say(f"serving ({tag}): batched {bat['wall_s']:.2f} s")
-    err = max(max_rel(a, b) for a, b in zip(phi_bat, phi_seq))
-    conv = all(st["converged"] for st in bat["stats"]) and all(st["converged"] for st in seq["stats"])
+    order = ("one", "batched", "batched", "one") if repeats >= 2 else ("one", "batched")
+    runs = {"one": [], "batched": []}
+    phi = {}
+    for mode in order:
+        say(f"serving ({tag}): {mode} ...")
+        if mode == "one":
+            phi[mode], d = one_at_a_time(reqs, plans, tol, max_iters, **kw)
+        else:
+            phi[mode], d = run_stream(reqs, plans, tol, max_iters, arena, **kw)
+        runs[mode].append(d)
+        say(f"serving ({tag}): {mode} {d['wall_s']:.2f} s")
+    err = max(max_rel(a, b) for a, b in zip(phi["batched"], phi["one"]))
+    conv = all(st["converged"] for d in runs["batched"] + runs["one"] for st in d["stats"])
+    one, bat = _pool(runs["one"], n_requests), _pool(runs["batched"], n_requests)
     out = {
         "workload": (f"{n_requests} independent fixed-source lattice solves to residual {tol:g} "
                      f"(4x4/8x8/16x16 cells, 10-50 layers, 1-7 groups, 8-32 azimuthal x 2-6 "
@@ -148,12 +172,11 @@ def compare(n_requests, arena_gib, tol=1e-6, max_iters=400, load=0.8, radial=0.0
         "arena_bytes": arena,
         "all_converged": conv,
         "max_rel_diff_batched_vs_alone": err,
-        "offline": {"batched": summarize(bat, n_requests),
-                    "one_at_a_time": summarize(seq, n_requests),
-                    "throughput_ratio": seq["wall_s"] / bat["wall_s"]},
+        "offline": {"order": list(order), "batched": bat, "one_at_a_time": one,
+                    "throughput_ratio": one["wall_s"] / bat["wall_s"]},
     }
     if poisson:
-        rate = load * n_requests / seq["wall_s"]
+        rate = load * n_requests / one["wall_s"]
         preqs = P.with_arrivals(probs, rate)
         say(f"serving ({tag}): Poisson arrivals at {rate:.1f}/s, one at a time ...")
         _, pseq = one_at_a_time(preqs, plans, tol, max_iters, use_arrivals=True, **kw)
