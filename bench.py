@@ -77,6 +77,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="lattice8")
     ap.add_argument("--oracle-iters", type=int, default=6)
+    ap.add_argument("--walk", choices=("auto", "lockstep", "lane"), default="auto",
+                    help="transport walk of the sweep (auto: the plan's choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=32,
                     help="requests in the serving comparison (0: skip it)")
@@ -104,7 +106,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     plan = moc.Plan(prob)
-    solver = moc.Solver(plan, fp64_boundary=False)
+    solver = moc.Solver(plan, fp64_boundary=False, walk=args.walk)
     solver.set_source(prob.q)
 
     # parity of the path being timed: GPU iterates vs the FP64 oracle
@@ -134,6 +136,7 @@ def main():
     sweep_s = st["sweep_ms_median"] * 1e-3
     achieved = BYTES_PER_SEG_GROUP * segg / sweep_s / 1e9
     traffic = load_traffic("k_sweep", args.workload)
+    solver_walk = solver.walk()
     solver.close()
     serving = None
     if args.serving_requests > 0:
@@ -163,6 +166,7 @@ def main():
             "max_rel_err_vs_fp64_oracle": parity,
             "parity_iterations": args.oracle_iters if parity is not None else None,
             "sweep_ms_median": st["sweep_ms_median"],
+            "walk": solver_walk,
         },
         "roofline": {
             "bound": "hbm",

@@ -194,6 +194,17 @@ MOC_API int moc_set_source(moc_solver *s, const double *q, size_t n);
  * Returns MOC_OK, or MOC_ENOTCONV when max_iters was reached (flux valid). */
 MOC_API int moc_solve(moc_solver *s, const moc_solve_opts *opts, moc_stats *stats);
 
+/* Transport walk of the FP32 sweep (groups of a line in one lane, G <= 8):
+ * 1 = lockstep (every lane of a wave takes each 2D segment together),
+ * 2 = per-lane (each lane takes one piece of its own line per step and moves
+ * on to its next 2D segment by itself), 0 = automatic (per-lane for G <= 8, the
+ * default).  Both walks give every line the same pieces in the same order:
+ * results differ only by the order of FP64 additions.  The batched serving
+ * sweep always takes the per-lane walk.  moc_solver_walk reports the walk in
+ * use (1 or 2). */
+MOC_API int moc_solver_set_walk(moc_solver *s, int walk);
+MOC_API int moc_solver_walk(const moc_solver *s, int *walk);
+
 /* Restart state (phi = 0, boundary psi = 0, iteration counter 0). */
 MOC_API int moc_reset(moc_solver *s);
 /* Run n further source iterations (source update, sweep, finalize) without a

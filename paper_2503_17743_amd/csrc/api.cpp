@@ -182,6 +182,19 @@ int moc_reset(moc_solver *sv) {
     return sv->s.reset();
 }
 
+int moc_solver_set_walk(moc_solver *sv, int walk) {
+    if (!sv) return fail(MOC_EINVAL, "NULL solver");
+    if (walk < 0 || walk > 2) return fail(MOC_EINVAL, "walk must be 0 (automatic), 1 (lockstep) or 2 (per-lane)");
+    sv->s.set_walk(walk);
+    return MOC_OK;
+}
+
+int moc_solver_walk(const moc_solver *sv, int *walk) {
+    if (!sv || !walk) return fail(MOC_EINVAL, "NULL argument");
+    *walk = sv->s.walk + 1;
+    return MOC_OK;
+}
+
 int moc_iterate(moc_solver *sv, int n, const moc_solve_opts *opts, moc_stats *stats) {
     if (!sv) return fail(MOC_EINVAL, "NULL solver");
     if (n < 1) return fail(MOC_EINVAL, "n must be >= 1");

@@ -41,6 +41,7 @@ struct WinArgs {
     const long long *filt_i0; // test hook: only lines [i0, i0+T) of it
     int Sw;                   // 2D segments per window
     int lstride;              // line stride inside a bundle (1: consecutive lines)
+    int walk;                 // transport walk of the FP32 one-chunk sweep: 0 lockstep, 1 per-lane
 };
 
 // Per-problem control of a batched step: the stopping rule and the state the

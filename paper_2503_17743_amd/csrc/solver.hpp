@@ -52,6 +52,9 @@ struct Solver {
     std::vector<hipEvent_t> events;
     int sw32 = 0, sw64 = 0;          // windowed sweep: 2D segments per window (0: direct path)
     int lstride = 1;                 // windowed sweep: line stride inside a bundle
+    int walk = 0;                    // transport walk in use: 0 lockstep, 1 per-lane
+    int walk_auto = 0;               // the plan's choice (set at upload)
+    void set_walk(int mode) { walk = mode == 0 ? walk_auto : mode - 1; }
     std::vector<long long> chunk_off, trk_off;
     std::vector<int> work_host;      // windowed-sweep work list (longest first)
     std::vector<float> work_cost;    // estimated cost of each work-list unit

@@ -441,9 +441,14 @@ __device__ inline double uniform_val(double v) {
 // EXPM 0: stable 1 - e^-tau; EXPM 1: 1 - hardware exp (precision study).
 // GC > 0: the group count is the compile-time constant GC (with C1), so the
 // per-group loops are straight-line code; GC = 0: G from the arguments.
-template <typename R, typename B, int MODE, int EXPM, bool BWD, bool C1, int GC = 0>
+// LANE (MODE 0, C1): every lane takes one piece of its own line per step and
+// moves on to its next 2D segment by itself (reading that segment's Sigma_t
+// row from LDS), instead of the whole wave taking every 2D segment together.
+// Both walks give every line the same pieces in the same order.
+template <typename R, typename B, int MODE, int EXPM, bool BWD, bool C1, int GC = 0, bool LANE = false>
 __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit,
                                            unsigned char *smem, bool flip = false) {
+    static_assert(!LANE || (MODE == 0 && C1), "the per-lane walk is the one-chunk transport sweep");
     const SweepArgs &a = wa.s;
     // boundary buffers of this sweep (flip: the descriptor's pair swapped)
     void *const psi_in = flip ? a.psi_out : a.psi_in;
@@ -612,6 +617,9 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                 while (hi2 - lo2 > 1) { const int m = (lo2 + hi2) >> 1; if (s_pos[m] < u_hi) lo2 = m; else hi2 = m; }
                 kb = lo2;
             }
+            // the same for every lane (the bounds came through lane shuffles)
+            ka = uniform(ka);
+            kb = uniform(kb);
             const bool starts = dir == 0 ? (ls >= wa_) : (le <= wb_);
             const bool ends = dir == 0 ? (le <= wb_) : (ls >= wa_);
             const long long slot = 2 * (a.trk_off[s] + i) + dir;
@@ -658,6 +666,79 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
             };
+            if constexpr (LANE) {
+                // the lane's first 2D segment: the one holding its start in
+                // sweep order (inside [ka, kb], since its extent is inside the
+                // bundle's)
+                const int kstep = dir ? -1 : 1;
+                int sg = dir ? kb : ka;
+                double e = 0.0;
+                bool fin = !active;
+                if (active) {
+                    const double l0 = wk.lcur;
+                    int lo2 = ka, hi2 = kb + 1;
+                    while (hi2 - lo2 > 1) {
+                        const int m = (lo2 + hi2) >> 1;
+                        if (dir ? (s_pos[m] < l0) : (s_pos[m] <= l0)) lo2 = m;
+                        else hi2 = m;
+                    }
+                    sg = lo2;
+                    e = dir ? fmax(s_pos[sg], ls) : fmin(s_pos[sg + 1], le);
+                }
+                // each lane walks its own segments, reading its segment's
+                // Sigma_t row from LDS; LDS indices of the lane's segment:
+                // tally / reduced source row and Sigma_t row
+                int lq = sg * KG + g0, lst = sg * G;
+                // every step takes a piece of at least one lane, and a line has
+                // at most (segments) + K + 2 pieces in the window: a bound on
+                // the steps that the walk never reaches
+                const int max_steps = 64 * (kb - ka + 1 + K + 2) + 8;
+                for (int step = 0; step < max_steps; ++step) {
+                    if (__ballot(!fin) == 0) break;
+                    if (!fin) {
+                        const bool cross = dir ? (wk.lnp > e) : (wk.lnp < e);
+                        const double lend = cross ? wk.lnp : e;
+                        const double l3 = (dir ? (wk.lcur - lend) : (lend - wk.lcur)) * secl;
+                        const bool valid = l3 >= kMinSeg;
+                        const int kz = min(max(wk.k, 0), K - 1);
+                        const int li = lq + (int)__umul24((unsigned)kz, (unsigned)G);
+                        const R lr = valid ? (R)l3 : (R)0;
+                        R qv[kGL], stv[kGL];
+#pragma unroll
+                        for (int j = 0; j < kGL; ++j)
+                            if (j < GL) {
+                                qv[j] = q_l[li + j];
+                                stv[j] = s_st[lst + j];
+                            }
+                        flush_pending();
+#pragma unroll
+                        for (int j = 0; j < kGL; ++j)
+                            if (j < GL) {
+                                const R f = kL2 ? (R)one_minus_exp2_f32((float)(stv[j] * lr))
+                                                : one_minus_exp<R>(stv[j] * lr, EXPM);
+                                const R d = fma(-Wr, qv[j], psi[j]) * f;
+                                psi[j] -= d;
+                                pend[j] = d;
+                            }
+                        pend_li = li;
+                        nseg += valid;
+                        wk.lcur = lend;
+                        if (cross) {
+                            wk.k += wk.kstep;
+                            wk.mnext += wk.kstep;
+                            wk.lnp = wk.mnext * wk.hc - wk.bc;
+                        } else if (sg == (dir ? ka : kb) || e == (dir ? ls : le)) {
+                            fin = true;      // the line leaves the bundle's segments here
+                        } else {
+                            sg += kstep;
+                            lq += kstep * KG;
+                            lst += kstep * G;
+                            const double sp = s_pos[dir ? sg : sg + 1];
+                            e = dir ? (sp > ls ? sp : ls) : (sp < le ? sp : le);
+                        }
+                    }
+                }
+            } else {
             const int nk = kb - ka + 1;
             for (int q = 0; q < nk; ++q) {
                 const int kk = dir ? (kb - q) : (ka + q);
@@ -704,6 +785,7 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                         }
                     pend_li = li;
                 });
+            }
             }
             flush_pending();
             if (MODE == 0 && active) {
@@ -785,6 +867,15 @@ __global__ __launch_bounds__(kWinThreads) __attribute__((amdgpu_waves_per_eu(4))
     else sweep_unit<float, B, MODE, EXPM, false, C1, GC>(wa, code, blockIdx.x, smem);
 }
 
+// The FP32 transport sweep with the per-lane walk (one-chunk lanes, G = GC).
+template <typename B, int GC>
+__global__ __launch_bounds__(kWinThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_win_lane(WinArgs wa) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int code = wa.work[blockIdx.x];
+    if (code & 1) sweep_unit<float, B, 0, 0, true, true, GC, true>(wa, code, blockIdx.x, smem);
+    else sweep_unit<float, B, 0, 0, false, true, GC, true>(wa, code, blockIdx.x, smem);
+}
+
 // FP64 arithmetic (precision reference): no register cap
 template <typename B, int MODE, bool C1>
 __global__ __launch_bounds__(kWinThreads) void k_sweep_win_f64(WinArgs wa) {
@@ -798,7 +889,8 @@ __global__ __launch_bounds__(kWinThreads) void k_sweep_win_f64(WinArgs wa) {
 // u_slot[u0 + b] and is (2D track, direction) u_code[u0 + b] of that problem;
 // every problem brings its own descriptor (pointers into its own workspace,
 // sizes, window length), so the units of all active problems run in one
-// launch (one launch per lane layout).
+// launch (one launch per lane layout; one-chunk problems take the
+// per-lane walk).
 template <bool C1>
 __global__ __launch_bounds__(kWinThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_win_multi(
     const WinArgs *__restrict__ descs, const int *__restrict__ u_slot, const int *__restrict__ u_code,
@@ -819,8 +911,8 @@ __global__ __launch_bounds__(kWinThreads) __attribute__((amdgpu_waves_per_eu(4))
         switch (wa.s.G) {
 #define MOC_MULTI_CASE(g)                                                                  \
     case g:                                                                                \
-        if (code & 1) sweep_unit<float, float, 0, 0, true, true, g>(wa, code, blockIdx.x, smem, flip);  \
-        else sweep_unit<float, float, 0, 0, false, true, g>(wa, code, blockIdx.x, smem, flip);          \
+        if (code & 1) sweep_unit<float, float, 0, 0, true, true, g, true>(wa, code, blockIdx.x, smem, flip); \
+        else sweep_unit<float, float, 0, 0, false, true, g, true>(wa, code, blockIdx.x, smem, flip);        \
         break;
             MOC_MULTI_CASE(1)
             MOC_MULTI_CASE(2)
@@ -1211,6 +1303,10 @@ int Solver::upload(const Plan &p) {
     sw32 = window_fit(p, false);
     sw64 = window_fit(p, true);
     lstride = p.lstride;
+    // the per-lane walk was measured faster on shallow and deep stacks alike
+    // (lattice8 / 32 / 64); it exists for the one-chunk lane layout
+    walk_auto = group_chunks(p.G) == 1 ? 1 : 0;
+    walk = walk_auto;
     std::vector<std::pair<double, int>> est(p.n2d);
     for (int64_t t = 0; t < p.n2d; ++t) {
         double lines = 0;
@@ -1262,6 +1358,17 @@ static void launch_win_c(const WinArgs &wa, unsigned nb, size_t lds, hipStream_t
         else k_sweep_win_f64<B, 0, C1><<<nb, kWinThreads, lds, st>>>(wa);
     } else if (mode == 1) {
         k_sweep_win<B, 1, 0, C1><<<nb, kWinThreads, lds, st>>>(wa);
+    } else if (expm == 0 && C1 && wa.walk == 1) {
+        switch (wa.s.G) {
+        case 1: k_sweep_win_lane<B, 1><<<nb, kWinThreads, lds, st>>>(wa); break;
+        case 2: k_sweep_win_lane<B, 2><<<nb, kWinThreads, lds, st>>>(wa); break;
+        case 3: k_sweep_win_lane<B, 3><<<nb, kWinThreads, lds, st>>>(wa); break;
+        case 4: k_sweep_win_lane<B, 4><<<nb, kWinThreads, lds, st>>>(wa); break;
+        case 5: k_sweep_win_lane<B, 5><<<nb, kWinThreads, lds, st>>>(wa); break;
+        case 6: k_sweep_win_lane<B, 6><<<nb, kWinThreads, lds, st>>>(wa); break;
+        case 7: k_sweep_win_lane<B, 7><<<nb, kWinThreads, lds, st>>>(wa); break;
+        default: k_sweep_win_lane<B, 8><<<nb, kWinThreads, lds, st>>>(wa); break;
+        }
     } else if (expm == 0) {
         // the transport sweep with the group count compiled in (G <= 8)
         switch (C1 ? wa.s.G : 0) {
@@ -1297,6 +1404,7 @@ void Solver::launch_sweep(SweepArgs a, bool fp64, const int *units, int n_units,
         wa.filt_i0 = filt_i0;
         wa.Sw = sw;
         wa.lstride = lstride;
+        wa.walk = walk;
         const unsigned nb = units ? (unsigned)n_units : (unsigned)(2 * info.n_2d_tracks);
         if (nb == 0) return;
         const size_t lds = win_lds_bytes(sw, K, info.n_groups, fp64 ? 8 : 4);

@@ -94,6 +94,8 @@ def lib():
         "moc_set_source": ([VP, VP, C.c_size_t], C.c_int),
         "moc_solve": ([VP, C.POINTER(SolveOpts), C.POINTER(Stats)], C.c_int),
         "moc_reset": ([VP], C.c_int),
+        "moc_solver_set_walk": ([VP, C.c_int], C.c_int),
+        "moc_solver_walk": ([VP, C.POINTER(C.c_int)], C.c_int),
         "moc_iterate": ([VP, C.c_int, C.POINTER(SolveOpts), C.POINTER(Stats)], C.c_int),
         "moc_get_flux": ([VP, VP, C.c_size_t], C.c_int),
         "moc_get_volumes": ([VP, VP, C.c_size_t], C.c_int),
@@ -200,7 +202,7 @@ class Plan:
 class Solver:
     """A plan bound to a device workspace (torch uint8 tensor) and a stream."""
 
-    def __init__(self, plan: Plan, device="cuda", workspace=None, fp64_boundary=None):
+    def __init__(self, plan: Plan, device="cuda", workspace=None, fp64_boundary=None, walk="auto"):
         import torch
         self.plan = plan
         self.info = plan.info
@@ -220,6 +222,8 @@ class Solver:
         self._h = h
         self.n_fsr = plan.info["n_fsr"]
         self.G = plan.info["n_groups"]
+        if walk != "auto":
+            self.set_walk(walk)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -246,6 +250,17 @@ class Solver:
 
     def reset(self):
         _check(lib().moc_reset(self._h))
+
+    WALKS = {"auto": 0, "lockstep": 1, "lane": 2}
+
+    def set_walk(self, walk="auto"):
+        """Transport walk of the FP32 one-chunk sweep: auto, lockstep or lane (per-lane)."""
+        _check(lib().moc_solver_set_walk(self._h, self.WALKS[walk]))
+
+    def walk(self):
+        w = C.c_int()
+        _check(lib().moc_solver_walk(self._h, C.byref(w)))
+        return "lockstep" if w.value == 1 else "lane"
 
     def iterate(self, n, sweep_fp64=False, exp_mode=0, stats=True):
         o = SolveOpts(0.0, 1, int(sweep_fp64), int(exp_mode))

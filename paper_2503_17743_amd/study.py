@@ -79,14 +79,14 @@ def precision(name, iters, fp64_boundary=None):
     return out
 
 
-def scale(name, iters):
+def scale(name, iters, walk="auto"):
     import torch
     prob = P.get(name)
     t0 = time.perf_counter()
     plan = moc.Plan(prob)
     t_plan = time.perf_counter() - t0
     _log(f"scale {name}: planned in {t_plan:.1f} s, workspace {plan.info['workspace_bytes'] / 1e9:.1f} GB")
-    s = moc.Solver(plan, fp64_boundary=False)
+    s = moc.Solver(plan, fp64_boundary=False, walk=walk)
     s.set_source(prob.q)
     torch.cuda.synchronize()
     hist, sweep_ms = [], []
@@ -105,7 +105,7 @@ def scale(name, iters):
     out = {"study": "scale", "workload": name, "iterations": iters, "plan_s": t_plan,
            "n_fsr": plan.info["n_fsr"], "n_3d_tracks": plan.info["n_3d_tracks"],
            "workspace_bytes": plan.info["workspace_bytes"],
-           "seg_group_updates_per_sweep": segg, "sweep_ms_median": med,
+           "seg_group_updates_per_sweep": segg, "sweep_ms_median": med, "walk": s.walk(),
            "seg_group_per_s_sweep": segg / (med * 1e-3),
            "seg_group_per_s_wall": segg * iters / wall, "wall_s": wall,
            "residual_history": hist, "link_errors": st["link_errors"],
@@ -120,12 +120,13 @@ def main(argv=None):
     ap.add_argument("study", choices=("precision", "scale"))
     ap.add_argument("--workload", default=None)
     ap.add_argument("--iters", type=int, default=None)
+    ap.add_argument("--walk", choices=("auto", "lockstep", "lane"), default="auto")
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
     if args.study == "precision":
         out = precision(args.workload or "lattice32", args.iters or 20)
     else:
-        out = scale(args.workload or "lattice64", args.iters or 50)
+        out = scale(args.workload or "lattice64", args.iters or 50, args.walk)
     print(json.dumps(out), flush=True)
 
 
