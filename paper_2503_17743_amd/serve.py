@@ -61,14 +61,28 @@ def one_at_a_time(reqs, plans, tol, max_iters, use_arrivals=False, log=None, log
 
 
 def run_stream(reqs, plans, tol, max_iters, arena_bytes, max_slots=64, use_arrivals=False,
-               fill_units=None, log=None, log_every=0):
+               fill_units=None, log=None, log_every=0, classes=1, split_units=None):
     """Submit each request at its arrival time (all at t=0 unless use_arrivals)
     and step the server until every request is done (progress as for
-    one_at_a_time)."""
-    srv = moc.Server(arena_bytes, max_slots=max_slots, fill_units=fill_units)
+    one_at_a_time).  classes=2: requests below split_units work units (default:
+    1/16 of the fill target) go to a second server with its own stream and a
+    quarter of the arena, so small requests step at their own rate while the
+    large ones' kernels run beside them."""
     n = len(reqs)
+    if classes == 2:
+        small_bytes = arena_bytes // 4
+        srvs = [moc.Server(arena_bytes - small_bytes, max_slots=max_slots, fill_units=fill_units),
+                moc.Server(small_bytes, max_slots=max_slots, fill_units=fill_units)]
+        if split_units is None:
+            import torch
+            cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+            split_units = (fill_units or 64 * cus) // 16
+        route = [1 if 2 * pl.info["n_2d_tracks"] < split_units else 0 for pl in plans]
+    else:
+        srvs = [moc.Server(arena_bytes, max_slots=max_slots, fill_units=fill_units)]
+        route = [0] * n
     arr = _arrivals(reqs, use_arrivals)
-    tickets: Dict[int, int] = {}
+    tickets: Dict[tuple, int] = {}
     done: Dict[int, tuple] = {}
     lat = np.zeros(n)
     segg = 0
@@ -79,26 +93,32 @@ def run_stream(reqs, plans, tol, max_iters, arena_bytes, max_slots=64, use_arriv
     while len(done) < n:
         now = time.perf_counter() - t0
         while nxt < n and arr[nxt] <= now:
-            tickets[srv.submit(plans[nxt], reqs[nxt].problem.q, tol, max_iters)] = nxt
+            k = route[nxt]
+            tickets[(k, srvs[k].submit(plans[nxt], reqs[nxt].problem.q, tol, max_iters))] = nxt
             nxt += 1
         if not tickets:
             time.sleep(max(0.0, min(arr[nxt] - now, 0.01)))
             continue
-        na, _ = srv.step()
+        na = 0
+        for k, srv in enumerate(srvs):
+            if any(kk == k for kk, _ in tickets):
+                a, _ = srv.step()
+                na += a
         steps += 1
         max_active = max(max_active, na)
         now = time.perf_counter() - t0
-        for tk in list(tickets):
-            res = srv.poll(tk)
+        for key in list(tickets):
+            res = srvs[key[0]].poll(key[1])
             if res is None:
                 continue
-            i = tickets.pop(tk)
+            i = tickets.pop(key)
             done[i] = res
             lat[i] = now - arr[i]
             segg += res[1]["seg_group_updates"] * res[1]["iters"]
             _progress(log, log_every, len(done), n, "batched")
     wall = time.perf_counter() - t0
-    srv.close()
+    for srv in srvs:
+        srv.close()
     return [done[i][0] for i in range(n)], {
         "wall_s": wall, "seg_group_updates": segg, "latency_s": lat.tolist(), "steps": steps,
         "max_active": max_active, "stats": [done[i][1] for i in range(n)]}
@@ -134,7 +154,7 @@ def _pool(runs, n):
 
 
 def compare(n_requests, arena_gib, tol=1e-6, max_iters=400, load=0.8, radial=0.05,
-            axial=0.2, poisson=True, log=None, log_every=0, repeats=2):
+            axial=0.2, poisson=True, log=None, log_every=0, repeats=2, two_class=True):
     """Continuous batching against one-at-a-time on the same seeded requests:
     first all arriving at once (throughput; with repeats=2 the runs go one,
     batched, batched, one, so that neither mode always runs on a GPU that has
@@ -175,6 +195,12 @@ def compare(n_requests, arena_gib, tol=1e-6, max_iters=400, load=0.8, radial=0.0
         "offline": {"order": list(order), "batched": bat, "one_at_a_time": one,
                     "throughput_ratio": one["wall_s"] / bat["wall_s"]},
     }
+    if two_class:
+        say(f"serving ({tag}): batched, two classes ...")
+        _, b2 = run_stream(reqs, plans, tol, max_iters, arena, classes=2, **kw)
+        say(f"serving ({tag}): batched, two classes {b2['wall_s']:.2f} s")
+        out["offline"]["batched_two_class"] = summarize(b2, n_requests)
+        out["offline"]["throughput_ratio_two_class"] = one["wall_s"] / b2["wall_s"]
     if poisson:
         rate = load * n_requests / one["wall_s"]
         preqs = P.with_arrivals(probs, rate)
@@ -186,6 +212,10 @@ def compare(n_requests, arena_gib, tol=1e-6, max_iters=400, load=0.8, radial=0.0
         out["poisson"] = {"rate_req_per_s": rate, "load": load,
                           "batched": summarize(pbat, n_requests),
                           "one_at_a_time": summarize(pseq, n_requests)}
+        if two_class:
+            _, p2 = run_stream(preqs, plans, tol, max_iters, arena, use_arrivals=True, classes=2, **kw)
+            say(f"serving ({tag}): Poisson batched, two classes {p2['wall_s']:.2f} s")
+            out["poisson"]["batched_two_class"] = summarize(p2, n_requests)
     return out
 
 
