@@ -95,6 +95,16 @@ int orc_volumes(const orc_model *m, double *vol);
 int orc_solve(const orc_model *m, const double *q, double tol, int max_iters,
               double *phi_out, double *res_hist, orc_result *res);
 
+/* Eigenvalue mode: power iteration on k-eff with fission source chi_g F_j / k,
+ * F_j = sum_g nu_sigma_f phi_j,g (nu_sigma_f, chi [M][G]).  From phi = 1,
+ * psi = 0, k = 1; the residual is the larger of the relative change of k and
+ * the largest change of the normalised fission source over fissile FSRs;
+ * stops when it is < tol (after the first iteration) or after max_iters.
+ * phi_out [n_fsr][G] unnormalised, *k_out. */
+int orc_solve_eigen(const orc_model *m, const double *nu_sigma_f, const double *chi, double tol,
+                    int max_iters, double *phi_out, double *k_out, double *res_hist,
+                    orc_result *res);
+
 /* One sweep of a sample of directed 3D tracks, with given reduced source qhat
  * [n_fsr][G] and incoming angular flux psi_in [n_items][G].  Tallies
  * acc [n_fsr][G] += W * delta_psi of the sampled tracks only and returns each

@@ -80,6 +80,8 @@ def lib():
         L.orc_segment_counts.argtypes = [C.c_void_p, C.c_void_p]
         L.orc_solve.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_int, C.c_void_p,
                                 C.c_void_p, P(_Result)]
+        L.orc_solve_eigen.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int,
+                                      C.c_void_p, P(C.c_double), C.c_void_p, P(_Result)]
         L.orc_sweep_sample.argtypes = [C.c_void_p, C.c_longlong, C.c_void_p, C.c_void_p,
                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_track_weight.argtypes = [C.c_void_p, C.c_longlong]
@@ -215,6 +217,24 @@ class Model:
         res = {f: getattr(r, f) for f, _ in _Result._fields_}
         res["residual_history"] = hist[:r.iters].copy()
         return phi, res
+
+    def solve_eigen(self, nu_sigma_f, chi, tol=1e-8, max_iters=1000):
+        """Power iteration on k-eff (see orc_solve_eigen); returns
+        (phi [n_fsr][G] unnormalised, k, result dict with residual_history)."""
+        G = self.prob.n_groups
+        nsf = np.ascontiguousarray(nu_sigma_f, dtype=np.float64).reshape(-1, G)
+        ch = np.ascontiguousarray(chi, dtype=np.float64).reshape(-1, G)
+        phi = np.zeros((self.info["n_fsr"], G))
+        hist = np.zeros(max_iters)
+        k = C.c_double()
+        r = _Result()
+        rc = lib().orc_solve_eigen(self._h, _ptr(nsf), _ptr(ch), float(tol), int(max_iters), _ptr(phi),
+                                   C.byref(k), _ptr(hist), C.byref(r))
+        if rc != 0:
+            raise ValueError(f"oracle eigenvalue solve failed: {rc}")
+        res = {f: getattr(r, f) for f, _ in _Result._fields_}
+        res["residual_history"] = hist[:r.iters].copy()
+        return phi, k.value, res
 
     def sweep_sample(self, tracks, dirs, qhat, psi_in):
         tracks = np.ascontiguousarray(tracks, dtype=np.int64)

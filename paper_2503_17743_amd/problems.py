@@ -216,6 +216,26 @@ def homogeneous(material_seed=2, n_groups=7, nx=2, pitch=1.0, height=2.0, n_laye
     return p
 
 
+def fission_data(prob: Problem, fissile=(0,), seed=7, k_target=1.1):
+    """Synthetic fission data for eigenvalue mode (no evaluated nuclear data):
+    nu_sigma_f [M, G] and chi [M, G].  Fissile materials produce neutrons in
+    proportion to a random profile rising towards the slow groups; chi is a
+    fast spectrum (weight 2^-g, normalised).  The profile is scaled so that
+    the material's own infinite-medium multiplication factor is k_target,
+    which keeps lattice eigenvalues near one."""
+    rng = np.random.default_rng(seed)
+    M, G = prob.n_materials, prob.n_groups
+    chi = np.tile(2.0 ** -np.arange(G), (M, 1))
+    chi /= chi.sum(axis=1, keepdims=True)
+    nsf = np.zeros((M, G))
+    for m in fissile:
+        shape = rng.uniform(0.2, 1.0, size=G) * np.linspace(0.5, 1.5, G)
+        A = np.diag(prob.sigma_t[m]) - prob.sigma_s[m].T
+        kinf = float(shape @ np.linalg.solve(A, chi[m]))
+        nsf[m] = shape * (k_target / kinf)
+    return nsf, chi
+
+
 def pure_absorber(n_groups=2, sigma=(0.7, 1.3), q=None, bc=(0, 0, 0, 0, 0, 0), **kw) -> Problem:
     """Homogeneous box with no scattering (a pure absorber), vacuum by default."""
     nx = kw.pop("nx", 2)

@@ -1,6 +1,7 @@
 """The pins catch plausible mistakes: the oracle is rebuilt with one planted
 mistake at a time (a slip in the reduced source, the scattering orientation,
-the track weight, the attenuation, the estimator or the volumes) and the pin
+the track weight, the attenuation, the estimator, the volumes or the
+fission source) and the pin
 suite must fail for every one of them."""
 import os
 import subprocess
@@ -19,6 +20,7 @@ MUTATIONS = {
     4: "linearised attenuation",
     5: "estimator without the 4 pi qhat term",
     6: "volumes from one sweep direction",
+    7: "fission source without 1/k (eigenvalue mode)",
 }
 
 

@@ -177,6 +177,36 @@ def test_infinite_medium_multigroup():
     np.testing.assert_allclose(phi, np.tile(ref, (p.n_fsr, 1)), rtol=1e-9)
 
 
+def test_eigen_infinite_medium_one_group():
+    """k-eff of an all-reflective homogeneous box, one group: the infinite
+    multiplication factor nu Sigma_f / (Sigma_t - Sigma_s) = 0.6 / 0.5, with a
+    flat flux."""
+    p = P.config_plain()
+    m = O.Model(p)
+    phi, k, res = m.solve_eigen([[0.6]], [[1.0]], tol=1e-11, max_iters=3000)
+    assert res["residual"] < 1e-11
+    assert abs(k - 1.2) < 1e-9
+    np.testing.assert_allclose(phi / phi.mean(), 1.0, rtol=1e-9)
+
+
+def test_eigen_infinite_medium_multigroup():
+    """Multigroup infinite medium: k-eff is the only non-zero eigenvalue of
+    (diag Sigma_t - Sigma_s^T)^-1 chi nuSigma_f^T (library eigenvalues), and
+    the spectrum is (diag Sigma_t - Sigma_s^T)^-1 chi."""
+    p = P.homogeneous(n_groups=4)
+    nsf, chi = P.fission_data(p, k_target=1.05)
+    m = O.Model(p, n_threads=4)
+    phi, k, res = m.solve_eigen(nsf, chi, tol=1e-11, max_iters=5000)
+    assert res["residual"] < 1e-11
+    A = np.diag(p.sigma_t[0]) - p.sigma_s[0].T
+    kref = max(np.linalg.eigvals(np.linalg.solve(A, np.outer(chi[0], nsf[0]))).real)
+    assert abs(k - kref) < 1e-9 * kref
+    assert abs(kref - 1.05) < 1e-12
+    spec = np.linalg.solve(A, chi[0])
+    got = phi / phi[:, :1]
+    np.testing.assert_allclose(got, np.tile(spec / spec[0], (p.n_fsr, 1)), rtol=1e-8)
+
+
 def test_single_segment_attenuation():
     """A box that is one FSR: every 3D track is one segment, so one sweep of a
     track reproduces the segment solution psi_in e^-tau + qhat (1 - e^-tau)."""
