@@ -205,6 +205,23 @@ MOC_API int moc_solve(moc_solver *s, const moc_solve_opts *opts, moc_stats *stat
 MOC_API int moc_solver_set_walk(moc_solver *s, int walk);
 MOC_API int moc_solver_walk(const moc_solver *s, int *walk);
 
+/* Eigenvalue mode: power iteration on k-eff (the multiplication factor the
+ * paper's validation reports, Table 2).  nu_sigma_f and chi are [M][G]
+ * (M = the plan's materials; finite, >= 0, nu_sigma_f not all zero), copied
+ * to the device.  From phi = 1, psi = 0, k = 1, every iteration puts
+ * chi_g F_j / k with F_j = sum_g nu_sigma_f phi_j,g in place of the fixed
+ * source (which it overwrites: call moc_set_source again before a
+ * fixed-source solve), runs one source iteration (source update, sweep,
+ * finalize), sets k <- k P_new / P_old with P = sum_j V_j F_j, and takes as
+ * residual the larger of |dk| / k and the largest change of the normalised
+ * fission source over fissile FSRs (1 at the first iteration).  Stops when
+ * the residual < tol after the first iteration (MOC_OK) or at max_iters
+ * (MOC_ENOTCONV; flux and k valid).  *k_eff receives k; the flux (not
+ * normalised) is read with moc_get_flux.  opts->sweep_fp64 selects the FP64
+ * sweep; EINVAL for bad data or when no FSR produces fission neutrons. */
+MOC_API int moc_solve_eigen(moc_solver *s, const double *nu_sigma_f, const double *chi,
+                            const moc_solve_opts *opts, double *k_eff, moc_stats *stats);
+
 /* Restart state (phi = 0, boundary psi = 0, iteration counter 0). */
 MOC_API int moc_reset(moc_solver *s);
 /* Run n further source iterations (source update, sweep, finalize) without a

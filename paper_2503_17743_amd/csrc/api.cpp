@@ -232,6 +232,34 @@ int moc_solve(moc_solver *sv, const moc_solve_opts *opts, moc_stats *stats) {
     return res < opts->tol ? MOC_OK : MOC_ENOTCONV;
 }
 
+int moc_solve_eigen(moc_solver *sv, const double *nu_sigma_f, const double *chi,
+                    const moc_solve_opts *opts, double *k_eff, moc_stats *stats) {
+    if (!sv || !nu_sigma_f || !chi || !k_eff) return fail(MOC_EINVAL, "NULL argument");
+    int rc = check_opts(opts);
+    if (rc) return rc;
+    moc::Solver &s = sv->s;
+    const size_t mg = (size_t)s.n_materials * s.info.n_groups;
+    bool any = false;
+    for (size_t i = 0; i < mg; ++i) {
+        if (!(nu_sigma_f[i] >= 0) || !std::isfinite(nu_sigma_f[i]) || !(chi[i] >= 0) || !std::isfinite(chi[i]))
+            return fail(MOC_EINVAL, "nu_sigma_f and chi must be finite and >= 0");
+        any = any || nu_sigma_f[i] > 0;
+    }
+    if (!any) return fail(MOC_EINVAL, "nu_sigma_f is zero everywhere");
+    double k = 0.0, res = 1.0;
+    int iters = 0;
+    rc = s.solve_eigen(nu_sigma_f, chi, *opts, &k, &res, &iters);
+    if (rc) return rc;
+    *k_eff = k;
+    if (stats) {
+        rc = s.read_stats(stats);
+        if (rc) return rc;
+        stats->iters = iters;
+        stats->residual = res;
+    }
+    return (iters > 1 && res < opts->tol) ? MOC_OK : MOC_ENOTCONV;
+}
+
 int moc_get_flux(const moc_solver *sv, double *host_out, size_t n) {
     if (!sv || !host_out) return fail(MOC_EINVAL, "NULL argument");
     const moc::Solver &s = sv->s;

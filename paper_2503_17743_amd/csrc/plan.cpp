@@ -544,6 +544,9 @@ Layout make_layout(const Plan &p, bool psi64) {
     l.psi_bytes = 2 * ((psi + 255) & ~size_t(255));
     l.off_work = take((size_t)2 * p.n2d * 4);
     l.off_scal = take(128 * 1024);
+    l.off_nusf = take((size_t)p.M * p.G * 8);
+    l.off_chi = take((size_t)p.M * p.G * 8);
+    l.off_fold = take((size_t)p.n_fsr * 8);
     l.n_item_cap = 512;
     l.off_items = take(l.n_item_cap * 8);
     l.off_psi_entry = take(l.n_item_cap * kItemStride * 8);

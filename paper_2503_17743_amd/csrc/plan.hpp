@@ -81,6 +81,9 @@ struct Layout {
     size_t off_q = 0, off_qhat32 = 0, off_qhat64 = 0, off_acc = 0, off_phi = 0, off_vol = 0;
     size_t off_psi0 = 0, off_psi1 = 0, psi_bytes = 0;
     size_t off_scal = 0;
+    // eigenvalue mode: nu Sigma_f and chi [M][G], fission production of the
+    // previous iterate [n_fsr]
+    size_t off_nusf = 0, off_chi = 0, off_fold = 0;
     // scratch for the test hooks: work list + entry/exit flux per (wave, lane);
     // the same region holds traced segments
     size_t off_items = 0, off_psi_entry = 0, off_psi_exitb = 0;

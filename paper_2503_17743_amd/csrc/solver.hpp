@@ -75,6 +75,10 @@ struct Solver {
     int iterate(int nit, const moc_solve_opts &o, bool time_sweep);
     int read_stats(moc_stats *st);
     int read_residual(double *r);
+    int n_materials = 0;
+    // eigenvalue mode (power iteration on k-eff); nusf, chi host [M][G]
+    int solve_eigen(const double *nusf, const double *chi, const moc_solve_opts &o, double *k_out,
+                    double *res_out, int *iters_out);
     int sweep_items(long long n_items, const long long *items, const double *qhat,
                     const double *psi_in, int fp64, double *acc_out, double *psi_out);
     int trace_tracks(long long n, const long long *ids, int cap, int *fsr, double *len,

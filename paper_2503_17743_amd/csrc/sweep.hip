@@ -46,7 +46,9 @@ constexpr size_t kScalBytes = 128 * 1024;   // scalar block of a workspace
 constexpr int kSlotStride = 16;   // doubles between slots (separate cache lines)
 
 // scalar accumulator layout inside the scalar block (doubles / u64)
-enum ScalarQ { Q_SIN = 0, Q_SOUT, Q_LEAK, Q_NSEG, Q_LINKERR, Q_BAL, Q_ABS, Q_SRC, Q_RES, Q_COUNT };
+enum ScalarQ { Q_SIN = 0, Q_SOUT, Q_LEAK, Q_NSEG, Q_LINKERR, Q_BAL, Q_ABS, Q_SRC, Q_RES,
+               Q_PNEW, Q_POLD, Q_SHAPE, Q_COUNT };
+static_assert(64 + (size_t)Q_COUNT * 64 * 16 <= kScalBytes / 8, "scalar slots exceed the scalar block");
 __host__ __device__ inline size_t slot_index(int q, int slot) {
     return 64 + ((size_t)q * kSlots + slot) * kSlotStride;
 }
@@ -1161,6 +1163,75 @@ __global__ void k_gather_residual(const FsrArgs *args, int n_slots, double *out,
     }
 }
 
+// ------------------------------------------------------------------ eigenvalue mode
+
+// The fission source chi_g F_j / k in place of the fixed source, with
+// F_j = sum_g' nuSigma_f,g' phi_j,g' of the current iterate; F_j is kept for
+// the production ratio and the shape residual.
+__global__ __launch_bounds__(256) void k_fission_source(FsrArgs a, double *q, const double *nusf,
+                                                        const double *chi, double inv_k, double *fold) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const int G = a.G;
+    const long long j = i / G;
+    const int g = (int)(i - j * G);
+    const int mat = a.reg_mat[j / a.K];
+    const double *ph = a.phi + j * G;
+    double F = 0.0;
+    for (int gp = 0; gp < G; ++gp) F += nusf[mat * G + gp] * ph[gp];
+    q[i] = chi[mat * G + g] * F * inv_k;
+    if (g == 0) fold[j] = F;
+}
+
+// Fission production of the previous and of the new iterate, sum_j V_j F_j,
+// into the Q_POLD / Q_PNEW slots (one atomic per wave).
+__global__ __launch_bounds__(256) void k_production(FsrArgs a, const double *nusf, const double *fold) {
+    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int G = a.G;
+    double pn = 0.0, po = 0.0;
+    if (j < a.n / G) {
+        const int mat = a.reg_mat[j / a.K];
+        double F = 0.0;
+        for (int g = 0; g < G; ++g) F += nusf[mat * G + g] * a.phi[j * G + g];
+        pn = a.vol[j] * F;
+        po = a.vol[j] * fold[j];
+    }
+    pn = wave_sum(pn);
+    po = wave_sum(po);
+    if ((threadIdx.x & 63) == 0) {
+        const int sl = (int)((blockIdx.x * 4 + (threadIdx.x >> 6)) % kSlots);
+        unsafeAtomicAdd(&a.scal[slot_index(Q_PNEW, sl)], pn);
+        unsafeAtomicAdd(&a.scal[slot_index(Q_POLD, sl)], po);
+    }
+}
+
+// Largest change of the normalised fission source over fissile FSRs,
+// |F_j(new) r - F_j(old)| / (F_j(new) r) with r = P_old / P_new, into the
+// Q_SHAPE slots (a max: the values are >= 0, so their bit patterns order).
+__global__ __launch_bounds__(256) void k_shape_residual(FsrArgs a, const double *nusf, const double *fold,
+                                                        double ratio) {
+    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int G = a.G;
+    double r = 0.0;
+    if (j < a.n / G) {
+        const int mat = a.reg_mat[j / a.K];
+        double F = 0.0;
+        for (int g = 0; g < G; ++g) F += nusf[mat * G + g] * a.phi[j * G + g];
+        if (F > 0.0) r = fabs(F * ratio - fold[j]) / (F * ratio);
+    }
+    r = wave_max(r);
+    if ((threadIdx.x & 63) == 0) {
+        const int sl = (int)((blockIdx.x * 4 + (threadIdx.x >> 6)) % kSlots);
+        atomicMax((unsigned long long *)&a.scal[slot_index(Q_SHAPE, sl)],
+                  (unsigned long long)__double_as_longlong(r));
+    }
+}
+
+__global__ void k_fill_f64(double *p, double v, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
 __global__ void k_fill_u32(unsigned *p, unsigned v, size_t n) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -1459,6 +1530,7 @@ int Solver::init(const Plan &p, char *workspace, size_t ws_bytes, hipStream_t st
     stream = st;
     P = p.P;
     K = p.K;
+    n_materials = p.M;
     H = p.H;
     h = p.h;
     std::memcpy(bc, p.bc, sizeof(bc));
@@ -1583,6 +1655,74 @@ int Solver::read_stats(moc_stats *st) {
         std::nth_element(v.begin(), v.begin() + v.size() / 2, v.end());
         st->sweep_ms_median = v[v.size() / 2];
     }
+    return MOC_OK;
+}
+
+// Eigenvalue mode: power iteration on k-eff.  From phi = 1, psi = 0, k = 1,
+// every iteration puts the fission source of the current iterate in place of
+// the fixed source, runs one source iteration (source update, sweep,
+// finalize), updates k by the ratio of fission production and takes as
+// residual the larger of the relative change of k and the largest change of
+// the normalised fission source (1 at the first iteration).
+int Solver::solve_eigen(const double *nusf, const double *chi, const moc_solve_opts &o, double *k_out,
+                        double *res_out, int *iters_out) {
+    const int G = info.n_groups;
+    const size_t mg = (size_t)n_materials * G;
+    double *d_nusf = ws_ptr<double>(ws, lay.off_nusf), *d_chi = ws_ptr<double>(ws, lay.off_chi);
+    double *d_fold = ws_ptr<double>(ws, lay.off_fold), *d_q = ws_ptr<double>(ws, lay.off_q);
+    HIPCHK(hipMemcpyAsync(d_nusf, nusf, mg * 8, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(d_chi, chi, mg * 8, hipMemcpyHostToDevice, stream));
+    int rc = reset();
+    if (rc) return rc;
+    const FsrArgs f = fsr_args();
+    const size_t nfg = (size_t)f.n;
+    k_fill_f64<<<(unsigned)std::min<size_t>((nfg + 255) / 256, 65536), 256, 0, stream>>>(f.phi, 1.0, nfg);
+    HIPCHK(hipGetLastError());
+    has_source = true;
+    const long long nfsr = info.n_fsr;
+    const unsigned fb = (unsigned)((nfg + 255) / 256), jb = (unsigned)((nfsr + 255) / 256);
+    std::vector<double> sl((size_t)kSlots * kSlotStride * 3);
+    // the three eigenvalue quantities sit next to each other in the scalar block
+    const size_t s0 = slot_index(Q_PNEW, 0);
+    auto read_slots = [&]() -> int {
+        HIPCHK(hipMemcpyAsync(sl.data(), ws + lay.off_scal + s0 * 8, sl.size() * 8, hipMemcpyDeviceToHost,
+                              stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        return MOC_OK;
+    };
+    auto slot = [&](int q, int i) { return sl[slot_index(q, i) - s0]; };
+    double k = 1.0, res = 1.0;
+    int it = 0;
+    for (it = 1; it <= o.max_iters; ++it) {
+        k_fission_source<<<fb, 256, 0, stream>>>(f, d_q, d_nusf, d_chi, 1.0 / k, d_fold);
+        HIPCHK(hipGetLastError());
+        rc = iterate(1, o, true);
+        if (rc) return rc;
+        k_production<<<jb, 256, 0, stream>>>(f, d_nusf, d_fold);
+        HIPCHK(hipGetLastError());
+        if ((rc = read_slots())) return rc;
+        double pn = 0.0, po = 0.0;
+        for (int i = 0; i < kSlots; ++i) {
+            pn += slot(Q_PNEW, i);
+            po += slot(Q_POLD, i);
+        }
+        if (!(po > 0.0) || !(pn > 0.0)) {
+            set_error("no fission production: nu_sigma_f is zero wherever there is flux");
+            return MOC_EINVAL;
+        }
+        const double kn = k * pn / po;
+        k_shape_residual<<<jb, 256, 0, stream>>>(f, d_nusf, d_fold, po / pn);
+        HIPCHK(hipGetLastError());
+        if ((rc = read_slots())) return rc;
+        double shape = 0.0;
+        for (int i = 0; i < kSlots; ++i) shape = std::max(shape, slot(Q_SHAPE, i));
+        res = (it == 1) ? 1.0 : std::max(shape, std::fabs(kn - k) / std::fabs(kn));
+        k = kn;
+        if (it > 1 && res < o.tol) break;
+    }
+    *k_out = k;
+    *res_out = res;
+    *iters_out = std::min(it, o.max_iters);
     return MOC_OK;
 }
 

@@ -94,6 +94,7 @@ def lib():
         "moc_set_source": ([VP, VP, C.c_size_t], C.c_int),
         "moc_solve": ([VP, C.POINTER(SolveOpts), C.POINTER(Stats)], C.c_int),
         "moc_reset": ([VP], C.c_int),
+        "moc_solve_eigen": ([VP, VP, VP, C.POINTER(SolveOpts), C.POINTER(C.c_double), C.POINTER(Stats)], C.c_int),
         "moc_solver_set_walk": ([VP, C.c_int], C.c_int),
         "moc_solver_walk": ([VP, C.POINTER(C.c_int)], C.c_int),
         "moc_iterate": ([VP, C.c_int, C.POINTER(SolveOpts), C.POINTER(Stats)], C.c_int),
@@ -247,6 +248,22 @@ class Solver:
         d = st.as_dict()
         d["converged"] = rc == MOC_OK
         return self.flux(), d
+
+    def solve_eigen(self, nu_sigma_f, chi, tol=1e-6, max_iters=1000, sweep_fp64=False):
+        """Power iteration on k-eff (moc_solve_eigen): (phi [n_fsr][G], not
+        normalised; k; stats).  Overwrites the fixed source."""
+        nsf = np.ascontiguousarray(nu_sigma_f, dtype=np.float64)
+        ch = np.ascontiguousarray(chi, dtype=np.float64)
+        if nsf.shape != ch.shape or nsf.ndim != 2 or nsf.shape[1] != self.G:
+            raise ValueError("nu_sigma_f and chi must both be [M][G]")
+        o = SolveOpts(float(tol), int(max_iters), int(sweep_fp64), 0)
+        k = C.c_double()
+        st = Stats()
+        rc = _check(lib().moc_solve_eigen(self._h, _p(nsf), _p(ch), C.byref(o), C.byref(k), C.byref(st)),
+                    allow=(MOC_ENOTCONV,))
+        d = st.as_dict()
+        d["converged"] = rc == MOC_OK
+        return self.flux(), k.value, d
 
     def reset(self):
         _check(lib().moc_reset(self._h))
