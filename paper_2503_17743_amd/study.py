@@ -7,6 +7,9 @@
   python -m paper_2503_17743_amd.study scale [--workload lattice64] [--iters 50]
       FP32 source iterations of the whole problem: time per sweep, residual
       history and the neutron balance of the last iteration.
+  python -m paper_2503_17743_amd.study eigen [--workload lattice8] [--iters 2000]
+      Power iteration on k-eff (synthetic fission data, fissile inclusions)
+      to 1e-6: k, iterations and time per iteration.
 
 Progress goes to stderr.
 """
@@ -114,10 +117,34 @@ def scale(name, iters, walk="auto"):
     return out
 
 
+def eigen(name, tol=1e-6, max_iters=2000, walk="auto"):
+    """Power iteration on k-eff of a lattice with synthetic fission data
+    (fissile inclusion material): k, iterations, time per iteration."""
+    import torch
+    prob = P.get(name)
+    nsf, chi = P.fission_data(prob)
+    plan = moc.Plan(prob)
+    s = moc.Solver(plan, fp64_boundary=False, walk=walk)
+    _log(f"eigen {name}: power iteration to {tol:g} ...")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    phi, k, st = s.solve_eigen(nsf, chi, tol=tol, max_iters=max_iters)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    segg = st["seg_group_updates"]
+    out = {"study": "eigen", "workload": name, "tol": tol, "k_eff": k, "iterations": st["iters"],
+           "converged": st["converged"], "residual": st["residual"], "wall_s": wall,
+           "ms_per_iteration": wall / st["iters"] * 1e3, "sweep_ms_median": st["sweep_ms_median"],
+           "seg_group_updates_per_sweep": segg,
+           "seg_group_per_s_wall": segg * st["iters"] / wall, "walk": s.walk()}
+    s.close()
+    return out
+
+
 def main(argv=None):
     import torch
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=("precision", "scale"))
+    ap.add_argument("study", choices=("precision", "scale", "eigen"))
     ap.add_argument("--workload", default=None)
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--walk", choices=("auto", "lockstep", "lane"), default="auto")
@@ -125,6 +152,8 @@ def main(argv=None):
     torch.cuda.set_device(0)
     if args.study == "precision":
         out = precision(args.workload or "lattice32", args.iters or 20)
+    elif args.study == "eigen":
+        out = eigen(args.workload or "lattice8", max_iters=args.iters or 2000)
     else:
         out = scale(args.workload or "lattice64", args.iters or 50, args.walk)
     print(json.dumps(out), flush=True)
