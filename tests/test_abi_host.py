@@ -147,3 +147,28 @@ def test_workspace_footprint_grows_with_problem():
     b = moc.Plan(P.config_lattice8()).info
     assert 0 < a["workspace_bytes"] < b["workspace_bytes"]
     assert b["psi_bytes"] == pytest.approx(2 * 2 * b["n_3d_tracks"] * b["n_groups"] * 4, rel=1e-3)
+
+
+def test_null_and_invalid_arguments_are_rejected_without_a_device():
+    """Entry points check their arguments before any device work: NULL
+    handles and out-of-range values give MOC_EINVAL (no GPU is needed)."""
+    L = moc.lib()
+    opts = moc.SolveOpts(1e-6, 10, 0, 0)
+    k = C.c_double()
+    nsf = np.ones(4)
+    assert L.moc_solve_eigen(None, moc._p(nsf), moc._p(nsf), C.byref(opts), C.byref(k), None) == moc.MOC_EINVAL
+    assert L.moc_solver_set_walk(None, 0) == moc.MOC_EINVAL
+    w = C.c_int()
+    assert L.moc_solver_walk(None, C.byref(w)) == moc.MOC_EINVAL
+    assert L.moc_server_set_fill(None, 1) == moc.MOC_EINVAL
+    done = C.c_int()
+    assert L.moc_server_query(None, C.c_ulonglong(1), C.byref(done)) == moc.MOC_EINVAL
+    assert L.moc_server_step(None, None, None) == moc.MOC_EINVAL
+    b = C.c_size_t()
+    assert L.moc_server_arena_overhead(0, C.byref(b)) == moc.MOC_EINVAL
+    assert L.moc_server_arena_overhead(64, C.byref(b)) == moc.MOC_OK and b.value > 0
+    bad_tau = np.array([-1.0], np.float32)
+    out = np.zeros(1, np.float32)
+    assert L.moc_eval_attenuation(moc._p(bad_tau), 1, 0, moc._p(out)) == moc.MOC_EINVAL
+    assert L.moc_eval_attenuation(moc._p(np.array([0.5], np.float32)), 1, 2, moc._p(out)) == moc.MOC_EINVAL
+    assert len(L.moc_last_error().decode()) > 0
