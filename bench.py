@@ -76,7 +76,9 @@ def main():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="lattice8")
-    ap.add_argument("--oracle-iters", type=int, default=6)
+    ap.add_argument("--oracle-iters", type=int, default=56,
+                    help="FP64 oracle iterations: the CPU baseline sample (about 10 s on 16 "
+                         "threads) and the parity check of the same GPU iterates")
     ap.add_argument("--walk", choices=("auto", "lockstep", "lane"), default="auto",
                     help="transport walk of the sweep (auto: the plan's choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
