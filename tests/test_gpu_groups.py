@@ -78,3 +78,24 @@ def test_many_groups_served_in_a_mix(moc):
         assert st_m["converged"] and st_a["converged"]
         assert st_m["iters"] == st_a["iters"]
         assert _rel(phi_m, phi_a) < 1e-5
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_direct_sweep_when_the_window_does_not_fit(moc, nthreads, fp64):
+    """160 layers x 48 groups: one 2D segment's reduced source and FP64 tally
+    (160 * 48 * 12 B = 92 KB) exceed the LDS window budget, so the sweep takes
+    the direct path (one wave per bundle, FP64 atomics per piece)."""
+    p = P.small_lattice(seed=50, n=2, height=40.0, n_layers=160, n_groups=48, n_azim=4, n_polar=2,
+                        radial=0.3, axial=0.5)
+    assert p.n_layers * p.n_groups * 12 > 78 * 1024
+    plan = moc.Plan(p)
+    s = moc.Solver(plan)
+    s.set_source(p.q)
+    om = O.Model(p, n_threads=nthreads)
+    st = s.iterate(2, sweep_fp64=fp64)
+    ophi, _ = om.solve(max_iters=2, tol=0.0)
+    err = _rel(s.flux(), ophi)
+    print(f"direct sweep fp64={fp64}: max rel err {err:.3e}")
+    assert err < (1e-10 if fp64 else 1e-5)
+    assert st["link_errors"] == 0
+    assert st["seg_group_updates"] == 2 * om.info["n_segments"] * p.n_groups
