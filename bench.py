@@ -89,8 +89,8 @@ def main():
                     help="first run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the sweep is single-GPU in this build "
-              "(multi-GPU angular decomposition is design-only)", file=sys.stderr)
+        print("bench.py measures one GPU: the sweep runs on a single GPU "
+              "(the multi-GPU angular decomposition is a design, not built)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
