@@ -28,16 +28,21 @@ def workload_desc(prob):
             f"{prob.n_polar} polar, {prob.radial_spacing}/{prob.axial_spacing} cm spacing")
 
 
-def load_traffic(kernel_name, workload):
-    """HBM bytes per launch measured by rocprofv3 PMC runs, if recorded."""
+def load_counters(workload):
+    """HBM bytes per launch and the measured limiters of the sweep (rocprofv3
+    PMC runs recorded under profiles/), or (None, None) when absent or taken
+    on a different sweep source."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
-        return None
+        return None, None
     with open(path) as f:
         rec = json.load(f)
     if rec.get("kernel_source_hash") != kernel_hash():
-        return None
-    return rec.get("bytes_per_launch")
+        return None, None
+    lim = rec.get("limiters")
+    if lim is not None:
+        lim = dict(lim, kernel=rec.get("kernel"), source=rec.get("source"))
+    return rec.get("bytes_per_launch"), lim
 
 
 def kernel_hash():
@@ -137,7 +142,7 @@ def main():
     value = segg * args.steps / elapsed
     sweep_s = st["sweep_ms_median"] * 1e-3
     achieved = BYTES_PER_SEG_GROUP * segg / sweep_s / 1e9
-    traffic = load_traffic("k_sweep", args.workload)
+    traffic, limiters = load_counters(args.workload)
     solver_walk = solver.walk()
     solver.close()
     serving = None
@@ -179,6 +184,9 @@ def main():
             "traffic": traffic,
         },
         "cpu_baseline": cpu,
+        # what bounds the sweep when the algorithmic HBM figure exceeds 1
+        # (LDS staging and L2 absorb the traffic): rocprofv3 counters
+        "counters": limiters,
         "serving": serving,
     }
     print(json.dumps(line), flush=True)
