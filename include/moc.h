@@ -117,7 +117,7 @@ typedef struct {
 
 /* Solve controls.  sweep_fp64 = 1 runs segment arithmetic and angular flux in
  * FP64 (precision study); exp_mode 0 = stable 1 - e^-tau (polynomial below
- * tau = 1/2, hardware exp2 above; within 4 ulp), 1 = the naive 1 - exp(-tau)
+ * tau = ln(2)/2, hardware exp2 above; within 4 ulp), 1 = the naive 1 - exp(-tau)
  * with the hardware exponential (precision study only). */
 typedef struct {
     double tol;                /* stop when the L-inf relative flux change < tol  */

@@ -56,22 +56,21 @@ __host__ __device__ inline size_t slot_index(int q, int slot) {
 // ------------------------------------------------------------------ helpers
 
 constexpr float kLog2e = 1.44269504088896341f;
-// 1 - e^{-tau} switches form at tau = 1/2, i.e. at u = tau log2(e) below
-constexpr float kSmallU = 0.72134752044448170f;
+// 1 - e^{-tau} switches form at u = tau log2(e) = 1/2 (tau = ln(2)/2)
+constexpr float kSmallU = 0.5f;
 
 // F = 1 - 2^{-u} for u >= 0 without cancellation (the attenuation factor
-// 1 - e^{-tau} of Eq. 3 at u = tau log2(e)).  Below u = log2(e)/2 (tau = 1/2)
-// F = u p(u), with p the degree-5 interpolant of (1 - 2^-u)/u at the
-// Chebyshev nodes of [0, log2(e)/2]; above it the hardware exp2 is used,
-// where F >= 0.39 limits the cancellation.  Measured against FP64 over
-// tau in [2^-30, 40] with u = tau log2(e) rounded to FP32: within 2 ulp.
+// 1 - e^{-tau} of Eq. 3 at u = tau log2(e)).  Below u = 1/2, F = u p(u), with
+// p the degree-4 interpolant of (1 - 2^-u)/u at the Chebyshev nodes of
+// [0, 1/2]; above it the hardware exp2 is used, where F >= 0.29 limits the
+// cancellation to about 2 ulp.  Measured against FP64 over tau in [2^-30, 40]
+// with u = tau log2(e) rounded to FP32: within 2 ulp.
 __device__ inline float one_minus_exp2_f32(float u) {
-    float p = -1.2459162e-4f;
-    p = fmaf(p, u, 1.3103603e-3f);
-    p = fmaf(p, u, -9.6096816e-3f);
-    p = fmaf(p, u, 5.5502694e-2f);
-    p = fmaf(p, u, -2.4022642e-1f);
-    p = fmaf(p, u, 6.9314718e-1f);
+    float p = 1.15544000e-3f;
+    p = fmaf(p, u, -9.54227522e-3f);
+    p = fmaf(p, u, 5.54907210e-2f);
+    p = fmaf(p, u, -2.40225673e-1f);
+    p = fmaf(p, u, 6.93147182e-1f);
     const float large = 1.0f - __builtin_amdgcn_exp2f(-u);
     return u < kSmallU ? u * p : large;
 }
