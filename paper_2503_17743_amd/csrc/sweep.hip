@@ -565,13 +565,16 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
             // different layers, so fewer lanes of one instruction add to the
             // same LDS tally entry.  S = ceil(lines / T), at most the lines
             // per layer, keeps the bundle count of consecutive bundles.
+            // The per-lane walk packs the lines of all stacks into bundles
+            // instead (the prefix then counts lines): lanes need no common
+            // polar angle there, and the stacks' partial bundles merge.
             int nb = 0, S = 1;
             if (hi >= lo) {
                 const int nl = hi - lo + 1;
                 S = min(Smax, (nl + T - 1) / T);
                 const int ST = S * T;
                 const int blocks = (nl + ST - 1) / ST;
-                nb = (blocks - 1) * S + min(S, nl - (blocks - 1) * ST);
+                nb = LANE ? nl : (blocks - 1) * S + min(S, nl - (blocks - 1) * ST);
             }
             int sc = nb;
             for (int o = 1; o < 64; o <<= 1) {
@@ -585,29 +588,78 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
             if (lane == 0) bpre[0] = 0;
         }
         __syncthreads();
-        const int total = bpre[P];
+        const int n_lines = bpre[P];     // per-lane walk: lines of all stacks
+        const int total = LANE ? (n_lines + T - 1) / T : bpre[P];
         for (int bnd = wave; bnd < total; bnd += kWinWaves) {
-            int n = 0;
-            while (bpre[n + 1] <= bnd) ++n;
-            n = uniform(n);
+            int n = 0, i = 0, nact = 0;
+            bool active;
+            if constexpr (LANE) {
+                // entry g of the window's packed list: stack n, and its line
+                // in the order of the strided bundles above (those bundles
+                // concatenated), so neighbouring lanes stay S lines apart
+                const int g = bnd * T + tr;
+                const int gg = min(g, n_lines - 1);
+                while (bpre[n + 1] <= gg) ++n;
+                const int lo = r_lo[n], nl = r_hi[n] - lo + 1, S = r_st[n];
+                const int ST = S * T, full = (nl - 1) / ST;     // complete blocks
+                const int p = gg - bpre[n];
+                const int b = min(p / ST, full);
+                const int within = p - b * ST;
+                int r, k;
+                if (b < full) {
+                    r = within / T;
+                    k = within - r * T;
+                } else {
+                    // last block: rem lines in min(S, rem) bundles, the first
+                    // x of them one line longer
+                    const int rem = nl - full * ST, q = rem / S, x = rem - q * S;
+                    if (within < x * (q + 1)) {
+                        r = within / (q + 1);
+                        k = within - r * (q + 1);
+                    } else {
+                        const int w2 = within - x * (q + 1);
+                        r = x + w2 / q;
+                        k = w2 - (w2 / q) * q;
+                    }
+                }
+                i = lo + b * ST + r + S * k;
+                active = g < n_lines && tr < T && ng > 0;
+            } else {
+                while (bpre[n + 1] <= bnd) ++n;
+                n = uniform(n);
+                const int bl = bnd - bpre[n];
+                const int S = uniform(r_st[n]);
+                const int i0 = uniform(r_lo[n] + (bl / S) * S * T + bl % S);
+                nact = uniform(min(T, (r_hi[n] - i0) / S + 1));    // lines in this bundle (>= 1)
+                i = i0 + S * tr;
+                active = (tr < nact) && ng > 0;
+            }
             const long long s = t * P + n;
             const int an = az * P + n;
             const double c = a.cot[an], ic = a.icot[an], secl = a.secl[an], W = a.wgt[an];
-            const int bl = bnd - bpre[n];
-            const int S = uniform(r_st[n]);
-            const int i0 = uniform(r_lo[n] + (bl / S) * S * T + bl % S);
-            const int nact = uniform(min(T, (r_hi[n] - i0) / S + 1));    // lines in this bundle (>= 1)
-            const int i = i0 + S * tr;
-            const bool active = (tr < nact) && ng > 0;
             const double base = line_base(a, s, i);
             double ls = 1e300, le = -1e300;
             if (active) clip_line(base, c, ic, Lt, a.H, ls, le);
-            // segments of the window touched by the bundle: the extents of
-            // consecutive lines of one stack move monotonically with the line
-            // index, so the first and last line bound them
-            const int last = (nact - 1) * C;
-            const double u_lo = fmax(fmin(__shfl(ls, 0, 64), __shfl(ls, last, 64)), wa_);
-            const double u_hi = fmin(fmax(__shfl(le, 0, 64), __shfl(le, last, 64)), wb_);
+            // segments of the window touched by the bundle
+            double u_lo, u_hi;
+            if constexpr (LANE) {
+                // lines of several stacks: the extremes over the wave
+                double mn = ls, mx = le;
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    mn = fmin(mn, __shfl_xor(mn, o, 64));
+                    mx = fmax(mx, __shfl_xor(mx, o, 64));
+                }
+                u_lo = fmax(mn, wa_);
+                u_hi = fmin(mx, wb_);
+            } else {
+                // the extents of consecutive lines of one stack move
+                // monotonically with the line index, so the first and last
+                // line bound them
+                const int last = (nact - 1) * C;
+                u_lo = fmax(fmin(__shfl(ls, 0, 64), __shfl(ls, last, 64)), wa_);
+                u_hi = fmin(fmax(__shfl(le, 0, 64), __shfl(le, last, 64)), wb_);
+            }
             int ka = 0, kb = nsw - 1;
             {
                 int lo2 = 0, hi2 = nsw;
