@@ -42,6 +42,7 @@ struct WinArgs {
     int Sw;                   // 2D segments per window
     int lstride;              // line stride inside a bundle (1: consecutive lines)
     int walk;                 // transport walk of the FP32 one-chunk sweep: 0 lockstep, 1 per-lane
+    int small_wg;             // per-lane walk in 256-thread workgroups (Sw sized for them)
 };
 
 // Per-problem control of a batched step: the stopping rule and the state the

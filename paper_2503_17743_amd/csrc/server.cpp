@@ -228,12 +228,19 @@ bool Server::admissible() const {
 int Server::rebuild() {
     const int n = (int)active.size();
     std::vector<int> blk(n + 1, 0);
-    size_t lds = 0;
+    // one-chunk problems with shallow stacks sweep in 256-thread workgroups
+    // (their own launch, shorter windows), like their one-at-a-time solves
+    auto small = [&](int i) {
+        const Solver &s = active[i]->solver;
+        return s.info.n_groups <= kGL && s.lane_sw >= 1;
+    };
+    size_t lds = 0, lds_small = 0;
     for (int i = 0; i < n; ++i) {
         Solver &s = active[i]->solver;
         const long long nfg = (long long)s.info.n_fsr * s.info.n_groups;
         blk[i + 1] = blk[i] + (int)((nfg + 255) / 256);
-        lds = std::max(lds, s.win_lds());
+        if (small(i)) lds_small = std::max(lds_small, s.lane_lds());
+        else lds = std::max(lds, s.win_lds());
     }
     // the work list: problem after problem, each problem's units longest
     // first and the problems in order of their longest unit, so the launch
@@ -250,15 +257,17 @@ int Server::rebuild() {
     auto one_chunk = [&](int i) { return active[i]->solver.info.n_groups <= kGL; };
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
         if (one_chunk(x) != one_chunk(y)) return one_chunk(x);
+        if (small(x) != small(y)) return small(x);
         return head(x) > head(y);
     });
     std::vector<int> us2, uc2;
-    int n_c1 = 0;
+    int n_c1 = 0, n_small = 0;
     for (int i : order) {
         const std::vector<int> &w = active[i]->solver.work_host;
         us2.insert(us2.end(), w.size(), i);
         uc2.insert(uc2.end(), w.begin(), w.end());
         if (one_chunk(i)) n_c1 += (int)w.size();
+        if (small(i)) n_small += (int)w.size();
     }
     if (!us2.empty()) {
         SRV_HIPCHK(hipMemcpyAsync(d_uslot, us2.data(), us2.size() * 4, hipMemcpyHostToDevice, stream));
@@ -271,6 +280,7 @@ int Server::rebuild() {
     for (int i = 0; i < n; ++i) {
         const Request *r = active[i];
         h_win[i] = r->solver.win_args_batched();
+        if (small(i)) h_win[i].Sw = r->solver.lane_sw;
         h_fsr[i] = r->solver.fsr_args();
         h_ctl[i] = SlotCtl{r->opts.tol, r->opts.max_iters, r->iters, 0, 0};
     }
@@ -290,8 +300,10 @@ int Server::rebuild() {
     batch.n_slots = n;
     batch.n_units = (int)us2.size();
     batch.n_units_c1 = n_c1;
+    batch.n_units_small = n_small;
     batch.fsr_blocks = blk[n];
     batch.lds = lds;
+    batch.lds_small = lds_small;
     for (int b = 0; b < 2; ++b) {
         if (exec[b]) {
             (void)hipGraphExecDestroy(exec[b]);

@@ -26,7 +26,9 @@ struct BatchStep {
     SlotCtl *ctl;               // [n_slots] stopping rule and state of each problem (advanced by the step)
     int n_slots, n_units, fsr_blocks;
     int n_units_c1;             // units [0, n_units_c1) belong to problems with G <= 8
-    size_t lds;                 // dynamic LDS of the batched sweep (max over problems)
+    int n_units_small;          // units [0, n_units_small) run in 256-thread workgroups
+    size_t lds;                 // dynamic LDS of the 512-thread batched sweeps (max over problems)
+    size_t lds_small;           // dynamic LDS of the 256-thread batched sweep
 };
 int launch_batch_step(const BatchStep &b, hipStream_t st);
 // test hook: the sweep's F(tau) on the device for host values
@@ -54,6 +56,8 @@ struct Solver {
     int lstride = 1;                 // windowed sweep: line stride inside a bundle
     int walk = 0;                    // transport walk in use: 0 lockstep, 1 per-lane
     int walk_auto = 0;               // the plan's choice (set at upload)
+    int lane_sw = 0;                 // per-lane walk: 2D segments per window of a 256-thread
+                                     // workgroup (0: such windows are too short, 512 threads)
     void set_walk(int mode) { walk = mode == 0 ? walk_auto : mode - 1; }
     std::vector<long long> chunk_off, trk_off;
     std::vector<int> work_host;      // windowed-sweep work list (longest first)
@@ -71,6 +75,7 @@ struct Solver {
     int window_size(bool fp64) const { return fp64 ? sw64 : sw32; }
     WinArgs win_args_batched() const;   // descriptor of the batched sweep (even orientation)
     size_t win_lds() const;
+    size_t lane_lds() const;            // LDS of a 256-thread per-lane window (lane_sw)
     int reset();
     int iterate(int nit, const moc_solve_opts &o, bool time_sweep);
     int read_stats(moc_stats *st);

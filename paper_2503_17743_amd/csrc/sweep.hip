@@ -41,6 +41,10 @@ constexpr double kFourPi = 12.566370614359172953850573533118;
 constexpr size_t kWinLdsBudget = 64 * 1024;
 constexpr size_t kWinLdsBudgetDeep = 78 * 1024;
 constexpr int kWinDeepBelow = 8;
+// Per-lane walk on shallow stacks: 256-thread workgroups with 40 KB windows
+// (four per CU), used when such a window still holds kWinSmallMinSw segments
+constexpr size_t kWinLdsBudgetSmall = 40 * 1024;
+constexpr int kWinSmallMinSw = 16;
 constexpr int kSlots = 64;        // spread of the scalar accumulators
 constexpr size_t kScalBytes = 128 * 1024;   // scalar block of a workspace
 constexpr int kSlotStride = 16;   // doubles between slots (separate cache lines)
@@ -446,7 +450,8 @@ __device__ inline double uniform_val(double v) {
 // moves on to its next 2D segment by itself (reading that segment's Sigma_t
 // row from LDS), instead of the whole wave taking every 2D segment together.
 // Both walks give every line the same pieces in the same order.
-template <typename R, typename B, int MODE, int EXPM, bool BWD, bool C1, int GC = 0, bool LANE = false>
+template <typename R, typename B, int MODE, int EXPM, bool BWD, bool C1, int GC = 0, bool LANE = false,
+          int NT = kWinThreads>
 __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit,
                                            unsigned char *smem, bool flip = false) {
     static_assert(!LANE || (MODE == 0 && C1), "the per-lane walk is the one-chunk transport sweep");
@@ -495,7 +500,7 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
     const int g0 = (lane - tr * C) * GL;
     const int ng = max(0, min(GL, G - g0));
 
-    for (int i = tid; i < Sw * KG; i += kWinThreads) acc_l[i] = 0.0;
+    for (int i = tid; i < Sw * KG; i += NT) acc_l[i] = 0.0;
 
     double s_in = 0.0, s_out = 0.0, leak = 0.0;
     long long nseg = 0, link_err = 0;
@@ -508,18 +513,18 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
         const double wb_ = (k0 + nsw < f1) ? a.seg_pos[k0 + nsw] : Lt;
         // stage the window: segment starts, regions, Sigma_t and the reduced
         // source of every FSR-group the window can touch
-        for (int i = tid; i < nsw; i += kWinThreads) {
+        for (int i = tid; i < nsw; i += NT) {
             s_pos[i] = a.seg_pos[k0 + i];
             s_reg[i] = a.seg_reg[k0 + i];
         }
         if (tid == 0) s_pos[nsw] = wb_;
         if (MODE == 0) {
-            for (int i = tid; i < nsw * G; i += kWinThreads) {
+            for (int i = tid; i < nsw * G; i += NT) {
                 const int kk = i / G;
                 const int m = a.reg_mat[a.seg_reg[k0 + kk]] * G + (i - kk * G);
                 s_st[i] = kL2 ? (R)(a.sigt64[m] * 1.4426950408889634) : sigt[m];
             }
-            for (int i = tid; i < nsw * KG; i += kWinThreads) {
+            for (int i = tid; i < nsw * KG; i += NT) {
                 const int kk = i / KG;
                 q_l[i] = qhat[(size_t)a.seg_reg[k0 + kk] * KG + (i - kk * KG)];
             }
@@ -590,7 +595,7 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
         __syncthreads();
         const int n_lines = bpre[P];     // per-lane walk: lines of all stacks
         const int total = LANE ? (n_lines + T - 1) / T : bpre[P];
-        for (int bnd = wave; bnd < total; bnd += kWinWaves) {
+        for (int bnd = wave; bnd < total; bnd += (NT / 64)) {
             int n = 0, i = 0, nact = 0;
             bool active;
             if constexpr (LANE) {
@@ -880,7 +885,7 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
         __syncthreads();
         // flush the window tally: one HBM atomic per touched FSR-group (the
         // volume tally has one entry per FSR, kept in the g = 0 slots)
-        for (int i = tid; i < nsw * KG; i += kWinThreads) {
+        for (int i = tid; i < nsw * KG; i += NT) {
             const double v = acc_l[i];
             if (v != 0.0) {
                 const int kk = i / KG;
@@ -898,7 +903,7 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
     const long long ns = wave_sum_ll(MODE == 1 ? (g0 == 0 ? nseg : 0) : nseg * ng);
     const long long le_ = wave_sum_ll(link_err);
     if (lane == 0) {
-        const int sl = (int)(((long long)unit * kWinWaves + wave) % kSlots);
+        const int sl = (int)(((long long)unit * (NT / 64) + wave) % kSlots);
         if (MODE == 0) {
             unsafeAtomicAdd(&a.scal[slot_index(Q_SIN, sl)], v_in);
             unsafeAtomicAdd(&a.scal[slot_index(Q_SOUT, sl)], v_out);
@@ -921,12 +926,28 @@ __global__ __launch_bounds__(kWinThreads) __attribute__((amdgpu_waves_per_eu(4))
 }
 
 // The FP32 transport sweep with the per-lane walk (one-chunk lanes, G = GC).
-template <typename B, int GC>
-__global__ __launch_bounds__(kWinThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_win_lane(WinArgs wa) {
+// NT threads per workgroup (512, or 256 with the shorter windows of shallow
+// stacks: fewer waves wait at each window's barrier).
+template <typename B, int GC, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_win_lane(WinArgs wa) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int code = wa.work[blockIdx.x];
-    if (code & 1) sweep_unit<float, B, 0, 0, true, true, GC, true>(wa, code, blockIdx.x, smem);
-    else sweep_unit<float, B, 0, 0, false, true, GC, true>(wa, code, blockIdx.x, smem);
+    if (code & 1) sweep_unit<float, B, 0, 0, true, true, GC, true, NT>(wa, code, blockIdx.x, smem);
+    else sweep_unit<float, B, 0, 0, false, true, GC, true, NT>(wa, code, blockIdx.x, smem);
+}
+
+template <typename B, int NT>
+static void launch_lane(const WinArgs &wa, unsigned nb, size_t lds, hipStream_t st) {
+    switch (wa.s.G) {
+    case 1: k_sweep_win_lane<B, 1, NT><<<nb, NT, lds, st>>>(wa); break;
+    case 2: k_sweep_win_lane<B, 2, NT><<<nb, NT, lds, st>>>(wa); break;
+    case 3: k_sweep_win_lane<B, 3, NT><<<nb, NT, lds, st>>>(wa); break;
+    case 4: k_sweep_win_lane<B, 4, NT><<<nb, NT, lds, st>>>(wa); break;
+    case 5: k_sweep_win_lane<B, 5, NT><<<nb, NT, lds, st>>>(wa); break;
+    case 6: k_sweep_win_lane<B, 6, NT><<<nb, NT, lds, st>>>(wa); break;
+    case 7: k_sweep_win_lane<B, 7, NT><<<nb, NT, lds, st>>>(wa); break;
+    default: k_sweep_win_lane<B, 8, NT><<<nb, NT, lds, st>>>(wa); break;
+    }
 }
 
 // FP64 arithmetic (precision reference): no register cap
@@ -942,10 +963,10 @@ __global__ __launch_bounds__(kWinThreads) void k_sweep_win_f64(WinArgs wa) {
 // u_slot[u0 + b] and is (2D track, direction) u_code[u0 + b] of that problem;
 // every problem brings its own descriptor (pointers into its own workspace,
 // sizes, window length), so the units of all active problems run in one
-// launch (one launch per lane layout; one-chunk problems take the
-// per-lane walk).
-template <bool C1>
-__global__ __launch_bounds__(kWinThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_win_multi(
+// launch (one launch per lane layout and workgroup size; one-chunk problems
+// take the per-lane walk, shallow ones in 256-thread workgroups).
+template <bool C1, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_win_multi(
     const WinArgs *__restrict__ descs, const int *__restrict__ u_slot, const int *__restrict__ u_code,
     const SlotCtl *__restrict__ ctl, int u0) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -964,8 +985,8 @@ __global__ __launch_bounds__(kWinThreads) __attribute__((amdgpu_waves_per_eu(4))
         switch (wa.s.G) {
 #define MOC_MULTI_CASE(g)                                                                  \
     case g:                                                                                \
-        if (code & 1) sweep_unit<float, float, 0, 0, true, true, g, true>(wa, code, blockIdx.x, smem, flip); \
-        else sweep_unit<float, float, 0, 0, false, true, g, true>(wa, code, blockIdx.x, smem, flip);        \
+        if (code & 1) sweep_unit<float, float, 0, 0, true, true, g, true, NT>(wa, code, blockIdx.x, smem, flip); \
+        else sweep_unit<float, float, 0, 0, false, true, g, true, NT>(wa, code, blockIdx.x, smem, flip);        \
         break;
             MOC_MULTI_CASE(1)
             MOC_MULTI_CASE(2)
@@ -979,8 +1000,8 @@ __global__ __launch_bounds__(kWinThreads) __attribute__((amdgpu_waves_per_eu(4))
         default: break;
         }
     } else {
-        if (code & 1) sweep_unit<float, float, 0, 0, true, false>(wa, code, blockIdx.x, smem, flip);
-        else sweep_unit<float, float, 0, 0, false, false>(wa, code, blockIdx.x, smem, flip);
+        if (code & 1) sweep_unit<float, float, 0, 0, true, false, 0, false, NT>(wa, code, blockIdx.x, smem, flip);
+        else sweep_unit<float, float, 0, 0, false, false, 0, false, NT>(wa, code, blockIdx.x, smem, flip);
     }
 }
 
@@ -1429,6 +1450,15 @@ int Solver::upload(const Plan &p) {
     // (lattice8 / 32 / 64); it exists for the one-chunk lane layout
     walk_auto = group_chunks(p.G) == 1 ? 1 : 0;
     walk = walk_auto;
+    lane_sw = 0;
+    if (walk_auto == 1 && p.P <= kMaxPolar) {
+        int max_seg = 1;
+        for (int64_t t = 0; t < p.n2d; ++t)
+            max_seg = std::max<int>(max_seg, (int)(p.seg_first[t + 1] - p.seg_first[t]));
+        int s = 0;
+        while (s < max_seg && win_lds_bytes(s + 1, p.K, p.G, 4) <= kWinLdsBudgetSmall) ++s;
+        if (s >= kWinSmallMinSw || (s >= 1 && s == max_seg)) lane_sw = s;
+    }
     std::vector<std::pair<double, int>> est(p.n2d);
     for (int64_t t = 0; t < p.n2d; ++t) {
         double lines = 0;
@@ -1481,16 +1511,8 @@ static void launch_win_c(const WinArgs &wa, unsigned nb, size_t lds, hipStream_t
     } else if (mode == 1) {
         k_sweep_win<B, 1, 0, C1><<<nb, kWinThreads, lds, st>>>(wa);
     } else if (expm == 0 && C1 && wa.walk == 1) {
-        switch (wa.s.G) {
-        case 1: k_sweep_win_lane<B, 1><<<nb, kWinThreads, lds, st>>>(wa); break;
-        case 2: k_sweep_win_lane<B, 2><<<nb, kWinThreads, lds, st>>>(wa); break;
-        case 3: k_sweep_win_lane<B, 3><<<nb, kWinThreads, lds, st>>>(wa); break;
-        case 4: k_sweep_win_lane<B, 4><<<nb, kWinThreads, lds, st>>>(wa); break;
-        case 5: k_sweep_win_lane<B, 5><<<nb, kWinThreads, lds, st>>>(wa); break;
-        case 6: k_sweep_win_lane<B, 6><<<nb, kWinThreads, lds, st>>>(wa); break;
-        case 7: k_sweep_win_lane<B, 7><<<nb, kWinThreads, lds, st>>>(wa); break;
-        default: k_sweep_win_lane<B, 8><<<nb, kWinThreads, lds, st>>>(wa); break;
-        }
+        if (wa.small_wg) launch_lane<B, 256>(wa, nb, lds, st);
+        else launch_lane<B, kWinThreads>(wa, nb, lds, st);
     } else if (expm == 0) {
         // the transport sweep with the group count compiled in (G <= 8)
         switch (C1 ? wa.s.G : 0) {
@@ -1517,10 +1539,14 @@ static void launch_win(const WinArgs &wa, unsigned nb, size_t lds, hipStream_t s
 
 void Solver::launch_sweep(SweepArgs a, bool fp64, const int *units, int n_units,
                           const int *filt_n, const long long *filt_i0) {
-    const int sw = window_size(fp64);
+    int sw = window_size(fp64);
+    // the per-lane walk of shallow stacks runs in 256-thread workgroups
+    const bool small_wg = !fp64 && a.mode == 0 && a.exp_mode == 0 && walk == 1 && lane_sw >= 1;
+    if (small_wg) sw = lane_sw;
     if (sw >= 1) {
         WinArgs wa;
         wa.s = a;
+        wa.small_wg = small_wg ? 1 : 0;
         wa.work = units ? units : ws_ptr<int>(ws, lay.off_work);
         wa.filt_n = filt_n;
         wa.filt_i0 = filt_i0;
@@ -1607,16 +1633,20 @@ WinArgs Solver::win_args_batched() const {
 }
 
 size_t Solver::win_lds() const { return win_lds_bytes(sw32, K, info.n_groups, 4); }
+size_t Solver::lane_lds() const { return win_lds_bytes(lane_sw, K, info.n_groups, 4); }
 
 int launch_batch_step(const BatchStep &b, hipStream_t st) {
     if (b.n_slots <= 0) return MOC_OK;
     k_clear_scal_multi<<<dim3(8, b.n_slots), 256, 0, st>>>(b.fsr_table, b.ctl, 128 * 1024 / 4);
     k_source_multi<<<b.fsr_blocks, 256, 0, st>>>(b.fsr_table, b.blk_pre, b.ctl, b.n_slots);
-    if (b.n_units_c1 > 0)
-        k_sweep_win_multi<true><<<b.n_units_c1, kWinThreads, b.lds, st>>>(b.win_table, b.u_slot, b.u_code,
-                                                                            b.ctl, 0);
+    if (b.n_units_small > 0)
+        k_sweep_win_multi<true, 256><<<b.n_units_small, 256, b.lds_small, st>>>(b.win_table, b.u_slot,
+                                                                               b.u_code, b.ctl, 0);
+    if (b.n_units_c1 > b.n_units_small)
+        k_sweep_win_multi<true, kWinThreads><<<b.n_units_c1 - b.n_units_small, kWinThreads, b.lds, st>>>(
+            b.win_table, b.u_slot, b.u_code, b.ctl, b.n_units_small);
     if (b.n_units > b.n_units_c1)
-        k_sweep_win_multi<false><<<b.n_units - b.n_units_c1, kWinThreads, b.lds, st>>>(
+        k_sweep_win_multi<false, kWinThreads><<<b.n_units - b.n_units_c1, kWinThreads, b.lds, st>>>(
             b.win_table, b.u_slot, b.u_code, b.ctl, b.n_units_c1);
     k_finalize_multi<<<b.fsr_blocks, 256, 0, st>>>(b.fsr_table, b.blk_pre, b.ctl, b.n_slots);
     k_gather_residual<<<(b.n_slots + 255) / 256, 256, 0, st>>>(b.fsr_table, b.n_slots, b.res_dev, b.ctl);
