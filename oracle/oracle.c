@@ -38,7 +38,9 @@
  * is a plausible slip in a formula; the pin tests must fail for every one.
  *   1 reduced source without the 1/(4 pi)    4 linearised attenuation (tau)
  *   2 scattering matrix transposed           5 estimator without 4 pi qhat
- *   3 track weight without sin(theta)        6 volumes from one direction */
+ *   3 track weight without sin(theta)        6 volumes from one direction
+ *   7 fission source without 1/k             8 azimuthal weights from the
+ *                                              desired (uncorrected) angles */
 #ifndef ORC_MUTATION
 #define ORC_MUTATION 0
 #endif
@@ -389,6 +391,11 @@ static int build_quadrature(struct orc_model *m, const orc_problem *p) {
     for (int a = 0; a < A4; ++a) {
         double prev = (a == 0) ? -m->phi[0] : m->phi[a - 1];
         double next = (a == A4 - 1) ? ORC_PI - m->phi[A4 - 1] : m->phi[a + 1];
+#if ORC_MUTATION == 8
+        /* the same rule on the desired angles: every gap is 2 pi / A */
+        prev = 2.0 * ORC_PI / m->A * (a - 0.5);
+        next = 2.0 * ORC_PI / m->A * (a + 1.5);
+#endif
         m->dphi[a] = 0.5 * (next - prev);
         m->dphi[A2 - 1 - a] = m->dphi[a];
     }
@@ -796,6 +803,23 @@ int orc_track_info(const orc_model *m, long long track, double *p01, long long *
         if (!m->traced) return -2;
         succ[0] = m->succ[2 * track]; succ[1] = m->succ[2 * track + 1];
     }
+    return 0;
+}
+
+int orc_entry_vacuum(const orc_model *m, long long track, int dir) {
+    if (track < 0 || track >= m->n3d || (dir != 0 && dir != 1)) return -1;
+    double p0[3], p1[3], d[3];
+    track_endpoints(m, track, p0, p1, d, NULL, NULL);
+    /* the directed track enters at p0 moving along d (forward) or at p1
+     * moving along -d (backward); through a box edge it enters through both
+     * faces, and a vacuum face among them gives no incoming flux */
+    const double *pe = dir ? p1 : p0;
+    double de[3] = {dir ? -d[0] : d[0], dir ? -d[1] : d[1], dir ? -d[2] : d[2]};
+    int fl[6];
+    int nf = faces_of(m, pe, de, 0, 3, fl);
+    if (nf < 1) return -2;
+    for (int i = 0; i < nf; ++i)
+        if (m->bc[fl[i]] == 0) return 1;
     return 0;
 }
 

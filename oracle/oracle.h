@@ -83,6 +83,11 @@ long long orc_trace_track(const orc_model *m, long long track, int *fsr, double 
  * Only valid after a traced build. */
 int orc_track_info(const orc_model *m, long long track, double *p01, long long *succ);
 
+/* 1 when directed track (track, dir) enters the box through a vacuum face
+ * (its incoming angular flux is zero), 0 when every face it enters through
+ * is reflective, <0 on error.  Works on untraced builds. */
+int orc_entry_vacuum(const orc_model *m, long long track, int dir);
+
 /* Number of segments of every stored 3D track [n_3d_tracks] (traced build). */
 int orc_segment_counts(const orc_model *m, long long *counts);
 

@@ -84,6 +84,7 @@ def lib():
                                       C.c_void_p, P(C.c_double), C.c_void_p, P(_Result)]
         L.orc_sweep_sample.argtypes = [C.c_void_p, C.c_longlong, C.c_void_p, C.c_void_p,
                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_entry_vacuum.argtypes = [C.c_void_p, C.c_longlong, C.c_int]
         L.orc_track_weight.argtypes = [C.c_void_p, C.c_longlong]
         L.orc_track_weight.restype = C.c_double
         _lib = L
@@ -187,6 +188,16 @@ class Model:
         if rc != 0:
             raise ValueError("track_info failed")
         return p[:3], p[3:], s
+
+    def entry_vacuum(self, tracks, dirs):
+        """Boolean per directed track: it enters through a vacuum face."""
+        out = np.zeros(len(tracks), bool)
+        for i, (t, d) in enumerate(zip(tracks, dirs)):
+            r = lib().orc_entry_vacuum(self._h, int(t), int(d))
+            if r < 0:
+                raise ValueError(f"entry_vacuum failed for track {t} dir {d}")
+            out[i] = r == 1
+        return out
 
     def weight(self, track: int) -> float:
         return lib().orc_track_weight(self._h, int(track))

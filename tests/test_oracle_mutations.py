@@ -1,7 +1,7 @@
 """The pins catch plausible mistakes: the oracle is rebuilt with one planted
 mistake at a time (a slip in the reduced source, the scattering orientation,
-the track weight, the attenuation, the estimator, the volumes or the
-fission source) and the pin
+the track weight, the attenuation, the estimator, the volumes, the
+fission source or the azimuthal weights) and the pin
 suite must fail for every one of them."""
 import os
 import subprocess
@@ -21,6 +21,7 @@ MUTATIONS = {
     5: "estimator without the 4 pi qhat term",
     6: "volumes from one sweep direction",
     7: "fission source without 1/k (eigenvalue mode)",
+    8: "azimuthal weights from the desired angles",
 }
 
 

@@ -47,6 +47,57 @@ def test_solid_angle_weights_sum_to_4pi(maker):
                                rtol=1e-13)
 
 
+# Trigonometric polynomials as {frequency: coefficient} cosine series on [0, pi):
+# cos^4 and cos^6, whose integrals over [0, pi) are pi times the constant term.
+_COS_SERIES = {"cos4": {0: 3 / 8, 2: 1 / 2, 4: 1 / 8},
+               "cos6": {0: 5 / 16, 2: 15 / 32, 4: 3 / 16, 6: 1 / 32}}
+
+
+def _series_derivative(c, x, d):
+    """d-th derivative of sum_n c_n cos(n x)."""
+    out = np.zeros_like(x)
+    shift = [np.cos, lambda t: -np.sin(t), lambda t: -np.cos(t), np.sin][d % 4]
+    for n, a in c.items():
+        if n == 0:
+            out += a if d == 0 else 0.0
+        else:
+            out += a * n ** d * shift(n * x)
+    return out
+
+
+@pytest.mark.parametrize("n,n_azim,spacing", [(3, 16, 0.5), (2, 16, 0.3), (4, 32, 0.3),
+                                              (5, 32, 0.7), (8, 16, 0.05)])
+def test_azimuthal_weights_are_midpoint_cells(n, n_azim, spacing):
+    """Azimuthal weights: each corrected azimuth carries the directions nearer
+    to it than to its neighbours (the cells end halfway between neighbouring
+    corrected angles, and at 0 and pi by the mirror symmetry of the laydown).
+    For such a rule the error of sum_m w_m f(phi_m) against int_0^pi f is the
+    sum over cells of the Taylor moments of f about each node,
+    sum_d f^(d)(phi_m) (r_m^(d+1) - (-l_m)^(d+1)) / (d+1)!, with l_m and r_m the
+    half gaps to the neighbouring angles; after the moments up to d = 3 what
+    is left is bounded by max|f^(4)| (l^5 + r^5) / 120 per cell.  Coarse
+    laydowns move the corrected angles far from the uniform grid, so weights
+    spread any other way (uniform 2 pi / A, or from the uncorrected angles)
+    miss this identity by far more than the bound."""
+    p = P.small_lattice(n=n)
+    p.n_azim = n_azim
+    p.radial_spacing = spacing
+    q = O.Model(p, trace=False).quadrature()
+    x, w = q["phi"], q["dphi"]
+    assert np.all(np.diff(x) > 0)
+    ext = np.concatenate([[-x[0]], x, [2 * math.pi - x[-1]]])
+    left = 0.5 * (ext[1:-1] - ext[:-2])
+    right = 0.5 * (ext[2:] - ext[1:-1])
+    for name, c in _COS_SERIES.items():
+        got = np.sum(w * _series_derivative(c, x, 0))
+        moments = sum(np.sum(_series_derivative(c, x, d) * (right ** (d + 1) - (-left) ** (d + 1)))
+                      / math.factorial(d + 1) for d in range(1, 4))
+        m4 = sum(abs(a) * k ** 4 for k, a in c.items())
+        bound = np.sum(m4 * (right ** 5 + left ** 5)) / 120.0
+        exact = math.pi * c[0]
+        assert abs(got + moments - exact) <= bound, (name, got + moments - exact, bound)
+
+
 # ---------------------------------------------------------------- laydown
 @pytest.mark.parametrize("maker", [P.config_plain, P.small_lattice, P.config_lattice8])
 def test_2d_laydown_tiles_and_links(maker):
@@ -109,6 +160,28 @@ def test_sector_volumes_match_analytic():
         local = r % rc
         ref = inner if local % 2 == 0 else outer
         assert abs(v[j] - ref) < 5e-3 * ref, (j, v[j], ref)
+
+
+def test_entry_vacuum_matches_links():
+    """A directed track starts from vacuum exactly when no other directed track
+    continues into it: the traced build finds successors by matching end
+    points and directions, the entry query looks only at the faces the track
+    enters through."""
+    p = P.small_lattice(n=2, height=2.0, n_layers=2)     # reflective sides, vacuum z
+    m = O.Model(p, n_threads=4)
+    n3 = m.info["n_3d_tracks"]
+    has_pred = np.zeros(2 * n3, bool)
+    for tr in range(n3):
+        _, _, succ = m.track_info(tr)
+        for s in succ:
+            if s >= 0:
+                assert not has_pred[s]
+                has_pred[s] = True
+    tracks = np.repeat(np.arange(n3), 2)
+    dirs = np.tile([0, 1], n3)
+    vac = m.entry_vacuum(tracks, dirs)
+    assert vac.any() and (~vac).any()
+    np.testing.assert_array_equal(vac, ~has_pred)
 
 
 # ---------------------------------------------------------------- tracing
