@@ -148,11 +148,20 @@ typedef struct {
  * ratio >= 1; material id out of range; bc not 0/1. */
 MOC_API int moc_plan_create(const moc_geometry *geom, const moc_tracking *trk, const moc_xs *xs,
                             moc_plan **out);
+/* Sizes of the plan and the device footprint of the data that section 3.1
+ * copies to the GPU for 3D tracing and the sweep (the admission key of the
+ * serving calls).  EINVAL on NULL. */
 MOC_API int moc_plan_query(const moc_plan *plan, moc_plan_info *out);
-MOC_API void moc_plan_destroy(moc_plan *plan);   /* NULL-safe */
+/* Frees the host plan (lifetime only; no step of the method).  NULL-safe. */
+MOC_API void moc_plan_destroy(moc_plan *plan);
 
-/* Planner introspection (host, no device needed).  Sizes follow
- * moc_plan_info; any pointer may be NULL to skip that output.
+/* Planner introspection (host, no device needed) of the quantities the paper
+ * defines and this library stores: the angular quadrature indexed by azimuth
+ * m and polar angle n (section 2.1, Eq. 2), the 2D tracks of section 3.1's
+ * CPU ray tracing, the z-stacks of Eq. 5 (section 2.2) laid out as the
+ * Z-STACK table of Eq. 13 (section 3.2), and the 2D segments.  Sizes follow
+ * moc_plan_info; any pointer may be NULL to skip that output; EINVAL for a
+ * NULL plan or a chunk out of range.
  *  quadrature: phi [n_azim/2] corrected azimuths, dphi [n_azim/2] azimuthal
  *    weights, spacing [n_azim/2] corrected radial spacing, cot [n_azim/2][n_polar]
  *    corrected polar cotangents, weight [n_azim/2][n_polar] track weights
@@ -178,23 +187,34 @@ MOC_API int moc_plan_chunk(const moc_plan *plan, long long chunk, long long *fir
 /* ---------------------------------------------------------------- solver */
 
 /* Bind a plan to a caller-owned device workspace and stream; uploads the plan
- * (2D segments, z-stack table, links, cross sections) and computes the
- * track-estimated FSR volumes with one volume sweep.  ENOMEM when ws_bytes <
+ * (2D segments, z-stack table, links, cross sections: the data section 3.1
+ * moves to the GPU) and computes the track-estimated FSR volumes V_j of the
+ * Eq. 4 estimator with one volume sweep.  ENOMEM when ws_bytes <
  * workspace_bytes.  With ws_bytes >= workspace_bytes_fp64 the boundary
  * angular flux is stored in FP64 (else FP32).  The plan may be destroyed
  * afterwards. */
 MOC_API int moc_solver_create(const moc_plan *plan, void *dev_workspace, size_t ws_bytes,
                               void *stream, moc_solver **out);
-MOC_API void moc_solver_destroy(moc_solver *s);   /* NULL-safe; does not free the workspace */
+/* Lifetime only: NULL-safe; does not free the caller's workspace. */
+MOC_API void moc_solver_destroy(moc_solver *s);
 
-/* Fixed volumetric isotropic source q [n_fsr][G] (>= 0), copied to the device. */
+/* Fixed volumetric isotropic source Q of Eq. 1 (section 2.1), per FSR and
+ * group: q [n_fsr][G] (finite, >= 0), copied to the device.  EINVAL for a
+ * wrong size or a negative / non-finite value. */
 MOC_API int moc_set_source(moc_solver *s, const double *q, size_t n);
 
-/* Source iteration from phi = 0, psi = 0 until residual < tol or max_iters.
- * Returns MOC_OK, or MOC_ENOTCONV when max_iters was reached (flux valid). */
+/* Source iteration (section 2.1: Eq. 3 along every characteristic of both
+ * directions, Eq. 4 scalar-flux estimate, repeated with the updated
+ * scattering source until the flux stops changing) from phi = 0, psi = 0
+ * until the residual max |phi_k - phi_{k-1}| / phi_k < tol or max_iters.
+ * Each iteration is three launches (source update, on-the-fly sweep of
+ * section 2.2 Eqs. 5-11, finalize); the host reads 8 bytes per iteration.
+ * Returns MOC_OK, or MOC_ENOTCONV when max_iters was reached (flux valid);
+ * EINVAL for bad options. */
 MOC_API int moc_solve(moc_solver *s, const moc_solve_opts *opts, moc_stats *stats);
 
-/* Transport walk of the FP32 sweep (groups of a line in one lane, G <= 8):
+/* How the FP32 sweep generates the 3D segments of section 2.2 (Eqs. 6-11,
+ * evaluated per line) for lines whose groups sit in one lane (G <= 8):
  * 1 = lockstep (every lane of a wave takes each 2D segment together),
  * 2 = per-lane (each lane takes one piece of its own line per step and moves
  * on to its next 2D segment by itself), 0 = automatic (per-lane for G <= 8, the
@@ -222,17 +242,26 @@ MOC_API int moc_solver_walk(const moc_solver *s, int *walk);
 MOC_API int moc_solve_eigen(moc_solver *s, const double *nu_sigma_f, const double *chi,
                             const moc_solve_opts *opts, double *k_eff, moc_stats *stats);
 
-/* Restart state (phi = 0, boundary psi = 0, iteration counter 0). */
+/* Restart the source iteration of section 2.1 (phi = 0, boundary psi = 0,
+ * iteration counter 0). */
 MOC_API int moc_reset(moc_solver *s);
-/* Run n further source iterations (source update, sweep, finalize) without a
- * host synchronisation between them; stats (optional) synchronises once. */
+/* Run n further source iterations (section 2.1, Eqs. 3-4; source update,
+ * sweep, finalize) without a host synchronisation between them; stats
+ * (optional) synchronises once.  EINVAL for n < 1 or bad options. */
 MOC_API int moc_iterate(moc_solver *s, int n, const moc_solve_opts *opts, moc_stats *stats);
 
+/* The scalar flux of the last iterate (Eq. 4, section 2.1), host_out
+ * [n_fsr][G] FP64; n must be n_fsr * G (EINVAL otherwise).  Synchronises. */
 MOC_API int moc_get_flux(const moc_solver *s, double *host_out, size_t n);
+/* The track-estimated FSR volumes V_j of Eq. 4, host_out [n_fsr].  Synchronises. */
 MOC_API int moc_get_volumes(const moc_solver *s, double *host_out, size_t n);
+/* Device address of the Eq. 4 scalar flux [n_fsr][G] FP64 inside the
+ * workspace (valid while the solver exists; no copy). */
 MOC_API int moc_flux_device_ptr(const moc_solver *s, const double **dev);
 
-/* Test hook: one sweep of the listed work items (2*chunk + dir) only, from a
+/* Test hook: the Eq. 3 sweep (section 2.1) of the listed work items
+ * (2*chunk + dir) only, with the kernels and launch layout of the full sweep
+ * restricted to them, from a
  * given reduced source qhat [n_fsr][G] (rounded to the sweep precision) and
  * incoming angular flux psi_in [n_items][tracks_per_wave][G] (lines beyond a
  * chunk's count are ignored).  Returns the FSR tallies acc [n_fsr][G]
@@ -242,7 +271,25 @@ MOC_API int moc_sweep_items(moc_solver *s, long long n_items, const long long *i
                             const double *qhat, const double *psi_in, int sweep_fp64,
                             double *acc_out, double *psi_out);
 
-/* Test hook: the 3D segments the GPU generates on the fly for stored tracks
+/* Test hook: the reduced source qhat = (sum_g' Sigma_s phi + Q) / (4 pi Sigma_t)
+ * (the flat-source term of Eq. 3) of the solver's last source update, as the
+ * sweep read it: fp64 = 0 gives the FP32 values of the FP32 sweep (widened),
+ * 1 the FP64 values.  host_out [n_fsr][G]; n must be n_fsr * G.
+ * Synchronises the stream. */
+MOC_API int moc_get_reduced_source(const moc_solver *s, int fp64, double *host_out, size_t n);
+
+/* Test hook: the incoming angular flux that the next source iteration's sweep
+ * reads for the directed 3D tracks slots[i] = 2 * stored track + dir (the
+ * boundary exchange of section 2.1's characteristic sweep, lagged one
+ * iteration).  out [n][G], widened from the storage precision.  Only tracks
+ * that enter through a reflective face carry a flux; the entries of tracks
+ * entering through a vacuum face are stale and are not read by the sweep.
+ * EINVAL for a slot outside [0, 2 * n_3d_tracks).  Synchronises the stream. */
+MOC_API int moc_get_boundary_flux(const moc_solver *s, long long n, const long long *slots,
+                                  double *out);
+
+/* Test hook: the 3D segments (section 2.2, Eqs. 5-11) the GPU generates on
+ * the fly for stored tracks
  * track_ids [n] (forward order): FSR ids and lengths written at
  * [i*cap, i*cap + count[i]) of fsr_out / len_out (count may exceed cap, then
  * only cap are written). */
@@ -268,18 +315,23 @@ MOC_API int moc_eval_attenuation(const float *tau, long long n, int exp_mode, fl
  * launches).  Calls from one thread at a time. */
 MOC_API int moc_server_create(void *dev_arena, size_t arena_bytes, int max_slots, void *stream,
                               moc_server **out);
-MOC_API void moc_server_destroy(moc_server *srv);   /* NULL-safe; waits for the stream */
+/* Lifetime only: NULL-safe; waits for the stream; the arena stays the caller's. */
+MOC_API void moc_server_destroy(moc_server *srv);
 /* Bytes of the arena the server keeps for its own tables (host-only query):
- * a request fits when its workspace_bytes fits in the rest. */
+ * a request fits when its workspace_bytes fits in the rest.  Serving
+ * bookkeeping, no step of the method. */
 MOC_API int moc_server_arena_overhead(int max_slots, size_t *bytes);
 
-/* Queue a request (FP32 sweep, stable exponential; opts->sweep_fp64 and
- * opts->exp_mode must be 0).  The plan and q [n_fsr][G] are copied.
- * ENOMEM if the request could never fit the arena. */
+/* Queue a request: one fixed-source problem (geometry, tracks and cross
+ * sections of the plan, source Q of Eq. 1) to be solved by the source
+ * iteration of section 2.1 (FP32 sweep, stable exponential; opts->sweep_fp64
+ * and opts->exp_mode must be 0).  The plan and q [n_fsr][G] are copied.
+ * ENOMEM if the request could never fit the arena; EINVAL for bad input. */
 MOC_API int moc_server_submit(moc_server *srv, const moc_plan *plan, const double *q,
                               const moc_solve_opts *opts, unsigned long long *ticket);
 
-/* One step: admit waiting requests in arrival order while a slot is free
+/* One step (one source iteration of section 2.1, Eqs. 3-4, for every active
+ * request): admit waiting requests in arrival order while a slot is free
  * and the workspace fits (a request may be overtaken by smaller ones at most
  * 8 times), run one source iteration of every active request in one batched
  * launch sequence, and retire requests whose residual < tol (after the first
@@ -292,12 +344,14 @@ MOC_API int moc_server_submit(moc_server *srv, const moc_plan *plan, const doubl
 MOC_API int moc_server_step(moc_server *srv, int *n_active, int *n_queued);
 
 /* MOC_EBUSY while the request is queued or running.  Once it has retired:
- * copies its stats and (if flux_out) its flux [n_fsr][G], releases it and
+ * copies its stats and (if flux_out) its Eq. 4 scalar flux [n_fsr][G]
+ * (n must then be n_fsr * G, else EINVAL), releases it and
  * returns MOC_OK (converged) or MOC_ENOTCONV (stopped at max_iters). */
 MOC_API int moc_server_poll(moc_server *srv, unsigned long long ticket, moc_stats *stats,
                             double *flux_out, size_t n);
 
-/* Admission policy: with max_units > 0, queued requests are admitted in
+/* Admission policy (serving bookkeeping, no step of the method): with
+ * max_units > 0, queued requests are admitted in
  * arrival order only while the active requests hold at most max_units work
  * units (two per 2D track of each request; a request above the limit runs
  * alone).  Large requests then run close to first-come-first-served and small
@@ -305,10 +359,13 @@ MOC_API int moc_server_poll(moc_server *srv, unsigned long long ticket, moc_stat
  * 0: admit whatever fits the arena. */
 MOC_API int moc_server_set_fill(moc_server *srv, long long max_units);
 
-/* Non-releasing status check: *done = 1 once the request has retired (its
- * result waits for moc_server_poll), 0 while queued or running. */
+/* Non-releasing status check (serving bookkeeping): *done = 1 once the
+ * request has retired (its result waits for moc_server_poll), 0 while queued
+ * or running; EINVAL for an unknown ticket. */
 MOC_API int moc_server_query(const moc_server *srv, unsigned long long ticket, int *done);
 
+/* Text of the calling thread's last error ("" after success); valid until
+ * that thread's next call.  Error reporting only. */
 MOC_API const char *moc_last_error(void);
 
 #ifdef __cplusplus

@@ -806,6 +806,30 @@ int orc_track_info(const orc_model *m, long long track, double *p01, long long *
     return 0;
 }
 
+int orc_sample_path_length(const orc_model *m, long long n_items, const long long *track,
+                           double *wl, long long *n_seg_out) {
+    long long total = 0, cap = 1 << 16;
+    int bad = 0;
+    int *f = malloc(sizeof(int) * cap);
+    double *l = malloc(sizeof(double) * cap);
+    for (long long it = 0; it < n_items && !bad; ++it) {
+        long long tr = track[it];
+        if (tr < 0 || tr >= m->n3d) { bad = 1; break; }
+        double p0[3], p1[3], d[3];
+        track_endpoints(m, tr, p0, p1, d, NULL, NULL);
+        long long ns = trace3d(m, p0, p1, f, l, cap);
+        if (ns > cap) { bad = 1; break; }
+        total += ns;
+        double w = orc_track_weight(m, tr);
+        /* the volume estimator of the track-length flux estimate, one
+         * direction of the listed tracks: sum of W l per FSR */
+        for (long long k = 0; k < ns; ++k) wl[f[k]] += w * l[k];
+    }
+    free(f); free(l);
+    if (n_seg_out) *n_seg_out = total;
+    return bad ? -1 : 0;
+}
+
 int orc_entry_vacuum(const orc_model *m, long long track, int dir) {
     if (track < 0 || track >= m->n3d || (dir != 0 && dir != 1)) return -1;
     double p0[3], p1[3], d[3];

@@ -83,6 +83,13 @@ long long orc_trace_track(const orc_model *m, long long track, int *fsr, double 
  * Only valid after a traced build. */
 int orc_track_info(const orc_model *m, long long track, double *p01, long long *succ);
 
+/* Path length of a sample of stored 3D tracks, one direction each: adds
+ * W l of every segment to wl [n_fsr] (FSR volumes restricted to the sample
+ * are wl / (4 pi) per direction).  Works on untraced builds (tracks traced by
+ * brute force).  <0 on error. */
+int orc_sample_path_length(const orc_model *m, long long n_items, const long long *track,
+                           double *wl, long long *n_seg_out);
+
 /* 1 when directed track (track, dir) enters the box through a vacuum face
  * (its incoming angular flux is zero), 0 when every face it enters through
  * is reflective, <0 on error.  Works on untraced builds. */

@@ -85,6 +85,8 @@ def lib():
         L.orc_sweep_sample.argtypes = [C.c_void_p, C.c_longlong, C.c_void_p, C.c_void_p,
                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_entry_vacuum.argtypes = [C.c_void_p, C.c_longlong, C.c_int]
+        L.orc_sample_path_length.argtypes = [C.c_void_p, C.c_longlong, C.c_void_p, C.c_void_p,
+                                             C.c_void_p]
         L.orc_track_weight.argtypes = [C.c_void_p, C.c_longlong]
         L.orc_track_weight.restype = C.c_double
         _lib = L
@@ -188,6 +190,19 @@ class Model:
         if rc != 0:
             raise ValueError("track_info failed")
         return p[:3], p[3:], s
+
+    def sample_path_length(self, tracks, wl=None):
+        """sum of W l per FSR over the listed tracks (one direction each);
+        accumulates into wl when given."""
+        tracks = np.ascontiguousarray(tracks, dtype=np.int64)
+        if wl is None:
+            wl = np.zeros(self.info["n_fsr"])
+        nseg = C.c_longlong(0)
+        rc = lib().orc_sample_path_length(self._h, len(tracks), _ptr(tracks), _ptr(wl),
+                                          C.byref(nseg))
+        if rc != 0:
+            raise ValueError("sample_path_length failed")
+        return wl
 
     def entry_vacuum(self, tracks, dirs):
         """Boolean per directed track: it enters through a vacuum face."""

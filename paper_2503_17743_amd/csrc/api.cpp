@@ -219,9 +219,7 @@ int moc_solve(moc_solver *sv, const moc_solve_opts *opts, moc_stats *stats) {
     if (rc) return rc;
     double res = 1.0;
     for (int k = 0; k < opts->max_iters; ++k) {
-        rc = s.iterate(1, *opts, true);
-        if (rc) return rc;
-        rc = s.read_residual(&res);
+        rc = s.solve_step(*opts, &res);
         if (rc) return rc;
         if (res < opts->tol) break;
     }
@@ -293,6 +291,40 @@ int moc_sweep_items(moc_solver *sv, long long n_items, const long long *items, c
     for (long long i = 0; i < n_items; ++i)
         if (items[i] < 0 || items[i] >= 2 * s.info.n_chunks) return fail(MOC_EINVAL, "work item out of range");
     return s.sweep_items(n_items, items, qhat, psi_in, sweep_fp64, acc_out, psi_out);
+}
+
+int moc_get_reduced_source(const moc_solver *sv, int fp64, double *host_out, size_t n) {
+    if (!sv || !host_out) return fail(MOC_EINVAL, "NULL argument");
+    if (fp64 != 0 && fp64 != 1) return fail(MOC_EINVAL, "fp64 must be 0 or 1");
+    const moc::Solver &s = sv->s;
+    if (n != (size_t)s.info.n_fsr * s.info.n_groups) return fail(MOC_EINVAL, "size must be n_fsr * n_groups");
+    hipError_t e;
+    if (fp64) {
+        e = hipMemcpyAsync(host_out, s.ws + s.lay.off_qhat64, n * 8, hipMemcpyDeviceToHost, s.stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s.stream);
+    } else {
+        std::vector<float> q32;
+        try {
+            q32.resize(n);
+        } catch (const std::bad_alloc &) {
+            return fail(MOC_ENOMEM, "host allocation failed");
+        }
+        e = hipMemcpyAsync(q32.data(), s.ws + s.lay.off_qhat32, n * 4, hipMemcpyDeviceToHost, s.stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s.stream);
+        if (e == hipSuccess)
+            for (size_t i = 0; i < n; ++i) host_out[i] = q32[i];
+    }
+    if (e != hipSuccess) return fail(MOC_EDEVICE, hipGetErrorString(e));
+    return MOC_OK;
+}
+
+int moc_get_boundary_flux(const moc_solver *sv, long long n, const long long *slots, double *out) {
+    if (!sv || (n > 0 && (!slots || !out))) return fail(MOC_EINVAL, "NULL argument");
+    if (n < 0) return fail(MOC_EINVAL, "n must be >= 0");
+    const moc::Solver &s = sv->s;
+    for (long long i = 0; i < n; ++i)
+        if (slots[i] < 0 || slots[i] >= 2 * s.info.n_3d_tracks) return fail(MOC_EINVAL, "slot out of range");
+    return const_cast<moc::Solver &>(s).gather_boundary(n, slots, out);
 }
 
 int moc_trace_tracks(moc_solver *sv, long long n, const long long *track_ids, int cap, int *fsr_out,

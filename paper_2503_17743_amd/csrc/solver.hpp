@@ -78,6 +78,17 @@ struct Solver {
     size_t lane_lds() const;            // LDS of a 256-thread per-lane window (lane_sw)
     int reset();
     int iterate(int nit, const moc_solve_opts &o, bool time_sweep);
+    // One source iteration for moc_solve: on a non-default stream a captured
+    // graph per boundary-buffer parity (source update, sweep between two
+    // timing events, finalize, residual fold, 8-byte copy to pinned host
+    // memory); else the same launches one by one.  *res receives the residual.
+    int solve_step(const moc_solve_opts &o, double *res);
+    hipGraphExec_t step_exec[2] = {nullptr, nullptr};
+    int step_key = -1;               // sweep precision / exp mode / walk the graphs were built for
+    bool step_graphs_failed = false; // capture unsupported: launch one by one
+    double *h_res = nullptr;         // pinned: the folded residual of the last step
+    hipEvent_t step_ev[2] = {nullptr, nullptr};
+    void drop_step_graphs();
     int read_stats(moc_stats *st);
     int read_residual(double *r);
     int n_materials = 0;
@@ -88,6 +99,8 @@ struct Solver {
                     const double *psi_in, int fp64, double *acc_out, double *psi_out);
     int trace_tracks(long long n, const long long *ids, int cap, int *fsr, double *len,
                      int *count);
+    // incoming boundary flux of the next sweep for directed slots (host out [n][G])
+    int gather_boundary(long long n, const long long *slots, double *out);
     ~Solver();
 };
 

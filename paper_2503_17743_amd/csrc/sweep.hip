@@ -1082,6 +1082,18 @@ __global__ void k_trace(SweepArgs a, const long long *tracks, long long ntr, int
     count[i] = m;
 }
 
+// ------------------------------------------------------------------ boundary hook
+
+// out[i][g] = buf[slots[i]][g], widened to FP64 (buf holds B values)
+template <typename B>
+__global__ void k_gather_slots(const B *buf, const long long *slots, long long n, int G, double *out) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * G) return;
+    const long long k = i / G;
+    const int g = (int)(i - k * G);
+    out[i] = (double)buf[slots[k] * G + g];
+}
+
 // ------------------------------------------------------------------ source / finalize
 
 
@@ -1175,8 +1187,17 @@ __global__ __launch_bounds__(256) void k_source(FsrArgs a, int scal_words) {
     source_elem(a, (long long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
+// The residual of a single solve folded on the device: the max over the
+// Q_RES slots into word 0 of the scalar block (never a slot), so the host
+// reads 8 bytes.
+__global__ void k_fold_residual(double *scal) {
+    double r = threadIdx.x < kSlots ? scal[slot_index(Q_RES, threadIdx.x)] : 0.0;
+    r = wave_max(r);
+    if (threadIdx.x == 0) scal[0] = r;
+}
+
 // Finalize; the residual is the max over the Q_RES slots (folded by the
-// reader: the host, or the batched residual gather).
+// reader: the host, the single-solve fold or the batched residual gather).
 __global__ __launch_bounds__(256) void k_finalize(FsrArgs a) {
     finalize_elem(a, (long long)blockIdx.x * blockDim.x + threadIdx.x, blockIdx.x);
 }
@@ -1697,7 +1718,79 @@ int Solver::iterate(int nit, const moc_solve_opts &o, bool time_sweep) {
     return MOC_OK;
 }
 
+void Solver::drop_step_graphs() {
+    for (int b = 0; b < 2; ++b)
+        if (step_exec[b]) {
+            (void)hipGraphExecDestroy(step_exec[b]);
+            step_exec[b] = nullptr;
+        }
+    step_key = -1;
+}
+
+int Solver::solve_step(const moc_solve_opts &o, double *res) {
+    const int key = (o.sweep_fp64 ? 1 : 0) | (o.exp_mode ? 2 : 0) | (walk << 2);
+    if (!h_res) HIPCHK(hipHostMalloc((void **)&h_res, 64, hipHostMallocDefault));
+    for (int b = 0; b < 2; ++b)
+        if (!step_ev[b]) HIPCHK(hipEventCreate(&step_ev[b]));
+    const FsrArgs f = fsr_args();
+    const unsigned fblocks = (unsigned)((f.n + 255) / 256);
+    // the launches of one iteration whose sweep reads psi0 (odd) or psi1 (even)
+    auto issue = [&](bool odd) -> int {
+        k_source<<<fblocks, 256, 0, stream>>>(f, (int)(kScalBytes / 4));
+        SweepArgs a = sweep_args(o.sweep_fp64, o.exp_mode);
+        a.psi_in = ws + (odd ? lay.off_psi0 : lay.off_psi1);
+        a.psi_out = ws + (odd ? lay.off_psi1 : lay.off_psi0);
+        HIPCHK(hipEventRecord(step_ev[0], stream));
+        launch_sweep(a, o.sweep_fp64 != 0);
+        HIPCHK(hipEventRecord(step_ev[1], stream));
+        k_finalize<<<fblocks, 256, 0, stream>>>(f);
+        k_fold_residual<<<1, 64, 0, stream>>>(f.scal);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(h_res, f.scal, 8, hipMemcpyDeviceToHost, stream));
+        return MOC_OK;
+    };
+    ++iter;
+    const bool odd = (iter % 2) == 1;
+    if (stream && !step_graphs_failed) {
+        if (key != step_key) {
+            drop_step_graphs();
+            for (int b = 0; b < 2 && !step_graphs_failed; ++b) {
+                hipGraph_t g = nullptr;
+                if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+                    step_graphs_failed = true;
+                    break;
+                }
+                const int rc = issue(b == 1);
+                const hipError_t e = hipStreamEndCapture(stream, &g);
+                if (rc || e != hipSuccess || !g ||
+                    hipGraphInstantiate(&step_exec[b], g, nullptr, nullptr, 0) != hipSuccess)
+                    step_graphs_failed = true;
+                if (g) (void)hipGraphDestroy(g);
+            }
+            (void)hipGetLastError();
+            if (step_graphs_failed) drop_step_graphs();
+            else step_key = key;
+        }
+    }
+    if (step_exec[odd ? 1 : 0]) {
+        HIPCHK(hipGraphLaunch(step_exec[odd ? 1 : 0], stream));
+    } else {
+        const int rc = issue(odd);
+        if (rc) return rc;
+    }
+    HIPCHK(hipStreamSynchronize(stream));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, step_ev[0], step_ev[1]));
+    sweep_ms.push_back(ms);
+    *res = (iter <= 1) ? 1.0 : *h_res;
+    return MOC_OK;
+}
+
 Solver::~Solver() {
+    drop_step_graphs();
+    for (int b = 0; b < 2; ++b)
+        if (step_ev[b]) (void)hipEventDestroy(step_ev[b]);
+    if (h_res) (void)hipHostFree(h_res);
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
 }
 
@@ -1890,6 +1983,28 @@ int Solver::sweep_items(long long n_items, const long long *items, const double 
     HIPCHK(hipMemcpyAsync(acc_out, ws + lay.off_acc, nfg * 8, hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
     return reset();
+}
+
+int Solver::gather_boundary(long long n, const long long *slots, double *out) {
+    if (n <= 0) return MOC_OK;
+    const int G = info.n_groups;
+    // the buffer the next iteration reads: psi0 after an even number of iterations
+    const char *buf = ws + ((iter % 2 == 0) ? lay.off_psi0 : lay.off_psi1);
+    // staging in the test-hook scratch: slot ids in the entry region, values in the exit region
+    const long long per = (long long)(lay.n_item_cap * kItemStride) / G;
+    long long *d_slots = ws_ptr<long long>(ws, lay.off_psi_entry);
+    double *d_out = ws_ptr<double>(ws, lay.off_psi_exitb);
+    for (long long b = 0; b < n; b += per) {
+        const long long nb = std::min(per, n - b);
+        HIPCHK(hipMemcpyAsync(d_slots, slots + b, nb * 8, hipMemcpyHostToDevice, stream));
+        const unsigned blocks = (unsigned)((nb * G + 255) / 256);
+        if (lay.psi64) k_gather_slots<double><<<blocks, 256, 0, stream>>>((const double *)buf, d_slots, nb, G, d_out);
+        else k_gather_slots<float><<<blocks, 256, 0, stream>>>((const float *)buf, d_slots, nb, G, d_out);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(out + b * G, d_out, (size_t)nb * G * 8, hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+    }
+    return MOC_OK;
 }
 
 int Solver::trace_tracks(long long n, const long long *ids, int cap, int *fsr, double *len,

@@ -103,6 +103,8 @@ def lib():
         "moc_flux_device_ptr": ([VP, C.POINTER(VP)], C.c_int),
         "moc_sweep_items": ([VP, C.c_longlong, VP, VP, VP, C.c_int, VP, VP], C.c_int),
         "moc_trace_tracks": ([VP, C.c_longlong, VP, C.c_int, VP, VP, VP], C.c_int),
+        "moc_get_reduced_source": ([VP, C.c_int, VP, C.c_size_t], C.c_int),
+        "moc_get_boundary_flux": ([VP, C.c_longlong, VP, VP], C.c_int),
         "moc_server_create": ([VP, C.c_size_t, C.c_int, VP, C.POINTER(VP)], C.c_int),
         "moc_server_destroy": ([VP], None),
         "moc_server_arena_overhead": ([C.c_int, C.POINTER(C.c_size_t)], C.c_int),
@@ -201,9 +203,15 @@ class Plan:
 
 
 class Solver:
-    """A plan bound to a device workspace (torch uint8 tensor) and a stream."""
+    """A plan bound to a device workspace (torch uint8 tensor) and a stream.
 
-    def __init__(self, plan: Plan, device="cuda", workspace=None, fp64_boundary=None, walk="auto"):
+    stream="own" (default) gives the solver a non-default torch stream of its
+    own, on which moc_solve runs each iteration as one captured HIP graph;
+    stream="current" uses torch's current stream (plain launches when that is
+    the default stream)."""
+
+    def __init__(self, plan: Plan, device="cuda", workspace=None, fp64_boundary=None, walk="auto",
+                 stream="own"):
         import torch
         self.plan = plan
         self.info = plan.info
@@ -216,7 +224,13 @@ class Solver:
         base = workspace.data_ptr()
         aligned = (base + 255) & ~255
         avail = workspace.numel() - (aligned - base)
-        self.stream = torch.cuda.current_stream(workspace.device)
+        if stream == "own":
+            # the workspace was allocated on the current stream: order the
+            # solver's stream after it
+            self.stream = torch.cuda.Stream(workspace.device)
+            self.stream.wait_stream(torch.cuda.current_stream(workspace.device))
+        else:
+            self.stream = torch.cuda.current_stream(workspace.device)
         h = VP()
         _check(lib().moc_solver_create(plan._h, VP(aligned), avail, VP(self.stream.cuda_stream),
                                        C.byref(h)))
@@ -228,6 +242,9 @@ class Solver:
 
     def close(self):
         if getattr(self, "_h", None):
+            # the workspace returns to torch's allocator with the tensor: let
+            # the solver's stream finish with it first
+            self.stream.synchronize()
             lib().moc_solver_destroy(self._h)
             self._h = None
 
@@ -310,6 +327,19 @@ class Solver:
         _check(lib().moc_sweep_items(self._h, len(items), _p(items), _p(qhat), _p(psi_in),
                                      int(sweep_fp64), _p(acc), _p(psi_out)))
         return acc, psi_out
+
+    def reduced_source(self, fp64=False):
+        """qhat [n_fsr][G] of the last source update, as the sweep read it."""
+        out = np.zeros((self.n_fsr, self.G))
+        _check(lib().moc_get_reduced_source(self._h, int(bool(fp64)), _p(out), out.size))
+        return out
+
+    def boundary_flux(self, slots):
+        """Incoming flux [n][G] the next sweep reads for directed slots 2*track+dir."""
+        slots = np.ascontiguousarray(slots, dtype=np.int64)
+        out = np.zeros((len(slots), self.G))
+        _check(lib().moc_get_boundary_flux(self._h, len(slots), _p(slots), _p(out)))
+        return out
 
     def trace_tracks(self, track_ids, cap=4096):
         ids = np.ascontiguousarray(track_ids, dtype=np.int64)

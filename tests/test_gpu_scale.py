@@ -1,15 +1,30 @@
 """Parity at full scale, where the oracle cannot run whole iterations.
 
 The full lattices are too large for the oracle's stored segments: it traces
-each sampled 3D track by brute force instead.  On a seeded sample of bundles,
-the HIP sweep (in the launch configuration of the full solve, restricted to
-the sample) must give the same outgoing angular flux and the same FSR tallies
-as the oracle for the same reduced source and incoming flux.  At lattice32
-the FP32 iterate is also compared with the FP64 sweep over the whole problem.
+each sampled 3D track by brute force instead.  On a seeded sample of more than
+1e5 directed tracks (whole work items: bundles of consecutive lines of one
+z-stack in one direction), the HIP sweep in the launch configuration of the
+full solve, restricted to the sample, must give the same outgoing angular flux
+of every track and the same FSR tallies as the oracle for the same inputs.
+The inputs are the solver's own state after whole source iterations: the
+reduced source of its last iteration and the boundary flux its next sweep
+reads (zero where a track enters through a vacuum face, which the oracle
+decides from the geometry).
+
+Tolerances.  An FP32 sweep of a line of n pieces rounds the flux once or
+twice per piece (relative 6e-8 each) and F(tau) to within 4 ulp; over the
+few hundred pieces of a lattice64 line that bounds the outgoing flux at a few
+1e-6 relative, and every flux and source here is positive, so the relative
+error of psi_out is well conditioned.  A tally sums W (psi - qhat) F(tau),
+whose terms change sign, so the tallies are compared through the FSR flux
+that the sample's own tracks estimate by Eq. 4,
+4 pi qhat + 4 pi acc / (Sigma_t sum W l) (path lengths from the oracle), a
+positive quantity held to the 1e-5 flux tolerance.
 """
 import numpy as np
 import pytest
 
+import bench
 from oracle import oracle as O
 from paper_2503_17743_amd import problems as P
 
@@ -25,7 +40,33 @@ def moc():
     return M
 
 
-def _sampled_parity(moc, name, n_items, fp64, seed):
+@pytest.mark.parametrize("name,iters", [("lattice32", 10), ("lattice64", 2)])
+def test_sampled_parity_from_the_iterate(moc, name, iters, nthreads):
+    import torch
+    prob = P.get(name)
+    plan = moc.Plan(prob)
+    s = moc.Solver(plan, fp64_boundary=False)
+    s.set_source(prob.q)
+    st = s.iterate(iters)
+    assert st["link_errors"] == 0
+    out, cpu, (gpsi, opsi, phi_g, phi_o) = bench.sampled_parity(prob, plan, s, 100000, seed=23,
+                                                                threads=nthreads)
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    print(name, out)
+    assert out["tracks"] >= 100000
+    # every track carries flux: the relative comparison is well conditioned
+    assert (opsi > 0).mean() > 0.99
+    assert out["max_rel_err_psi_out"] < 2e-6
+    assert out["tallies_outside_sample"] == 0
+    # the FSR flux the sampled tracks estimate, held to the flux tolerance
+    assert out["max_rel_err_sample_fsr_flux"] < 1e-5
+
+
+def _random_input_parity(moc, name, n_items, fp64, seed):
+    """Random reduced source and entry flux (not an iterate): the FP64 sweep
+    against the oracle, which pins the segment geometry to FP64 rounding."""
     import torch
     prob = P.get(name)
     plan = moc.Plan(prob)
@@ -56,27 +97,23 @@ def _sampled_parity(moc, name, n_items, fp64, seed):
     return acc, oacc, gpsi, opsi
 
 
-@pytest.mark.parametrize("name,n_items,fp64", [
-    ("lattice32", 300, False),
-    ("lattice32", 120, True),
-    ("lattice64", 200, False),
-])
-def test_sampled_parity_full_scale(moc, name, n_items, fp64):
-    acc, oacc, gpsi, opsi = _sampled_parity(moc, name, n_items, fp64, seed=11)
-    # FP64: segment end points on tracks up to ~45 cm long agree to ~1e-12 cm
-    # (FP64 rounding of two different constructions), which moves the
-    # outgoing flux by up to ~1e-11 relative after ~300 segments
-    tol = 1e-10 if fp64 else 2e-6
-    np.testing.assert_allclose(gpsi, opsi, rtol=tol, atol=tol * np.abs(opsi).max())
+def test_fp64_sweep_random_inputs_lattice32(moc):
+    acc, oacc, gpsi, opsi = _random_input_parity(moc, "lattice32", 120, True, seed=11)
+    # segment end points on tracks up to ~45 cm long agree to ~1e-12 cm (FP64
+    # rounding of two different constructions), which moves the outgoing flux
+    # by up to ~1e-11 relative after ~300 segments
+    np.testing.assert_allclose(gpsi, opsi, rtol=1e-10, atol=1e-10 * np.abs(opsi).max())
     nz = np.abs(oacc) > 0
     assert (np.abs(acc[~nz]) == 0).all()
-    scale = np.abs(oacc).max()
-    np.testing.assert_allclose(acc, oacc, rtol=0, atol=(1e-10 if fp64 else 1e-5) * scale)
+    big = np.abs(oacc) >= 1e-3 * np.abs(oacc).max()
+    np.testing.assert_allclose(acc[big], oacc[big], rtol=1e-9)
+    np.testing.assert_allclose(acc, oacc, rtol=0, atol=1e-10 * np.abs(oacc).max())
 
 
 def test_lattice32_fp32_iterate_matches_fp64_sweep(moc):
-    """Ten source iterations of the whole lattice32 problem: the FP32 sweep's
-    iterate is within 1e-5 (max over all FSR-groups) of the FP64 sweep's."""
+    """Precision evidence (not parity): ten source iterations of the whole
+    lattice32 problem; the FP32 sweep's iterate is within 1e-5 (max over all
+    FSR-groups) of the FP64 sweep's."""
     from paper_2503_17743_amd import study
     out = study.precision("lattice32", 10)
     print(out)

@@ -162,6 +162,15 @@ def test_sector_volumes_match_analytic():
         assert abs(v[j] - ref) < 5e-3 * ref, (j, v[j], ref)
 
 
+def test_sample_path_length_gives_the_volumes():
+    """Path length of every track traced on the fly, both directions, over
+    4 pi: the track-estimated volumes of the stored segments."""
+    p = P.small_lattice()
+    m = O.Model(p, n_threads=4)
+    wl = m.sample_path_length(np.arange(m.info["n_3d_tracks"]))
+    np.testing.assert_allclose(2.0 * wl / (4 * math.pi), m.volumes(), rtol=1e-12)
+
+
 def test_entry_vacuum_matches_links():
     """A directed track starts from vacuum exactly when no other directed track
     continues into it: the traced build finds successors by matching end
