@@ -303,6 +303,16 @@ MOC_API int moc_trace_tracks(moc_solver *s, long long n, const long long *track_
  * device buffers (not part of the solve path); synchronous. */
 MOC_API int moc_eval_attenuation(const float *tau, long long n, int exp_mode, float *out);
 
+/* The same evaluation for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no device allocation and no free.  tau and out are host arrays
+ * as above; the values are staged through a fixed array of 2^20 inputs and
+ * 2^20 outputs that each device holds from the first call on it until the
+ * process ends.  EINVAL for n > 2^20 (nothing is evaluated).  Synchronous on
+ * the calling thread's current device; calls that overlap on one device
+ * (from several threads) share that array and race. */
+MOC_API int moc_eval_attenuation_noalloc(const float *tau, long long n, int exp_mode, float *out);
+
 /* ---------------------------------------------------------------- serving */
 
 /* Continuous batching of independent fixed-source solves on one GPU (the

@@ -347,4 +347,14 @@ int moc_eval_attenuation(const float *tau, long long n, int exp_mode, float *out
     return moc::eval_attenuation(tau, n, exp_mode, out);
 }
 
+int moc_eval_attenuation_noalloc(const float *tau, long long n, int exp_mode, float *out) {
+    if (n < 0 || (n > 0 && (!tau || !out))) return fail(MOC_EINVAL, "NULL argument or n < 0");
+    if (exp_mode != 0 && exp_mode != 1) return fail(MOC_EINVAL, "exp_mode must be 0 or 1");
+    if (n > moc::kNoAllocMaxTau)
+        return fail(MOC_EINVAL, "n exceeds the fixed staging capacity (2^20 values per call)");
+    for (long long i = 0; i < n; ++i)
+        if (!(tau[i] >= 0.0f) || !std::isfinite(tau[i])) return fail(MOC_EINVAL, "tau must be finite and >= 0");
+    return moc::eval_attenuation_noalloc(tau, n, exp_mode, out);
+}
+
 }  // extern "C"

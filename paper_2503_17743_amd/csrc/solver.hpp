@@ -33,6 +33,10 @@ struct BatchStep {
 int launch_batch_step(const BatchStep &b, hipStream_t st);
 // test hook: the sweep's F(tau) on the device for host values
 int eval_attenuation(const float *tau, long long n, int exp_mode, float *out);
+// the same without device allocation: staged through a fixed per-device array
+// of kNoAllocMaxTau inputs and outputs
+constexpr long long kNoAllocMaxTau = 1LL << 20;
+int eval_attenuation_noalloc(const float *tau, long long n, int exp_mode, float *out);
 // 2D segments per LDS window of the windowed sweep (0: does not fit)
 int window_fit(const Plan &p, bool fp64);
 

@@ -1034,6 +1034,60 @@ int eval_attenuation(const float *tau, long long n, int exp_mode, float *out) {
     return MOC_OK;
 }
 
+// ------------------------------------------------------------------ F(tau) hook without allocation
+
+// Staging of moc_eval_attenuation_noalloc, one copy per device for the life of
+// the process: tau in [0, kNoAllocMaxTau), F(tau) in [kNoAllocMaxTau, 2 kNoAllocMaxTau).
+// Host code never uses this name as an address: the device address comes from
+// hipGetSymbolAddress, once per device, and is kept in g_scratch_dev.
+static __device__ __align__(256) float scratch[2 * kNoAllocMaxTau];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+int eval_attenuation_noalloc(const float *tau, long long n, int exp_mode, float *out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        set_error(hipGetErrorString(e));
+        return MOC_EDEVICE;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device index beyond the library's per-device table");
+        return MOC_EDEVICE;
+    }
+    float *buf = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_dev[dev]) {
+            void *p = nullptr;
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess) {
+                set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+                return MOC_EDEVICE;
+            }
+            g_scratch_dev[dev] = static_cast<float *>(p);
+        }
+        buf = g_scratch_dev[dev];
+    }
+    if (n <= 0) return MOC_OK;
+    // every element read below is written first: nothing has to start at zero
+    e = hipMemcpy(buf, tau, (size_t)n * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        k_eval_attenuation<<<(unsigned)((n + 255) / 256), 256>>>(buf, buf + kNoAllocMaxTau, n, exp_mode);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpy(out, buf + kNoAllocMaxTau, (size_t)n * 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        set_error(hipGetErrorString(e));
+        return MOC_EDEVICE;
+    }
+    return MOC_OK;
+}
+
 // ------------------------------------------------------------------ trace hook
 
 // One thread per requested stored track (forward): the same piece generation

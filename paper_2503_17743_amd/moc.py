@@ -109,6 +109,7 @@ def lib():
         "moc_server_destroy": ([VP], None),
         "moc_server_arena_overhead": ([C.c_int, C.POINTER(C.c_size_t)], C.c_int),
         "moc_eval_attenuation": ([VP, C.c_longlong, C.c_int, VP], C.c_int),
+        "moc_eval_attenuation_noalloc": ([VP, C.c_longlong, C.c_int, VP], C.c_int),
         "moc_server_query": ([VP, C.c_ulonglong, C.POINTER(C.c_int)], C.c_int),
         "moc_server_set_fill": ([VP, C.c_longlong], C.c_int),
         "moc_server_submit": ([VP, VP, VP, C.POINTER(SolveOpts), C.POINTER(C.c_ulonglong)], C.c_int),
