@@ -135,6 +135,8 @@ typedef struct {
     unsigned long long seg_group_updates; /* per sweep: directed 3D segments x G  */
     unsigned long long link_errors;       /* exits whose successor was not found  */
     double sweep_ms_median;    /* median sweep-kernel time over the iterations    */
+                               /* (moc_solve with graph-captured iterations: the  */
+                               /* median time of a whole captured iteration)      */
 } moc_stats;
 
 /* ---------------------------------------------------------------- plan */
@@ -223,7 +225,52 @@ MOC_API int moc_solve(moc_solver *s, const moc_solve_opts *opts, moc_stats *stat
  * sweep always takes the per-lane walk.  moc_solver_walk reports the walk in
  * use (1 or 2). */
 MOC_API int moc_solver_set_walk(moc_solver *s, int walk);
+/* Workgroup size of the per-lane sweep and the window of 2D segments its LDS
+ * holds (the tally and reduced source of every layer and group of the
+ * window's segments, section 2.1 Eqs. 3-4): 0 = automatic (256 threads with
+ * 40 KB windows on shallow stacks, 1024 threads with up to 156 KB windows on
+ * deep ones, else 512 threads with 64-78 KB), or 256, 512, 1024 to force one.
+ * EINVAL for other values or when no window of that size fits.  Drops any
+ * segment store.  moc_solver_window reports the size and the segments per
+ * window in use. */
+MOC_API int moc_solver_set_window(moc_solver *s, int threads);
+MOC_API int moc_solver_window(const moc_solver *s, int *threads, int *segments);
 MOC_API int moc_solver_walk(const moc_solver *s, int *walk);
+
+/* Stored-segment sweep (the paper's EXP method with its memory management,
+ * section 4.2): the 3D pieces of the units (2D track, direction) with the
+ * largest footprint are generated once and kept in the caller's device
+ * buffer dev_store (store_bytes, 256-byte aligned; caller-owned, kept alive
+ * while the solver uses it), taken in decreasing footprint while they fit;
+ * later FP32 per-lane sweeps replay them with a transport-only kernel and
+ * sweep the remaining units on the fly, in that order on the solver's stream.
+ * Results equal those of the on-the-fly sweep up to the order of FP64
+ * additions.  The store serves the FP32 per-lane sweep only (G <= 8); the
+ * FP64 sweep, the lockstep walk and the test hooks sweep on the fly.
+ * dev_store = NULL or store_bytes = 0 drops the store.  info (optional)
+ * reports what was stored and, once the units were counted (a buffer of at
+ * least 20 bytes per unit), the buffer size that would hold them all.  EINVAL when the per-lane sweep does not apply.
+ * Changing the schedule drops the store. */
+typedef struct {
+    long long units_stored, units_total;
+    unsigned long long wave_steps_stored, wave_steps_total;  /* 64-lane steps of the walk */
+    size_t bytes_used;
+    size_t bytes_all;          /* buffer that would hold every unit (0 if not counted) */
+} moc_store_info;
+MOC_API int moc_solver_store_segments(moc_solver *s, void *dev_store, size_t store_bytes,
+                                      moc_store_info *info);
+
+/* Schedule of the work units (load balancing, paper section 4.3).  order:
+ * 0 = decreasing work (lines x 2D segments; the default), 1 = natural (2D
+ * track order of Eq. 13), 2 = decreasing work in groups of the resident
+ * workgroup count with every other group reversed (the paper's alternating
+ * sort).  persistent: 0 = one workgroup per unit, dispatched in list order;
+ * 1 = a grid of the resident workgroup count, workgroup b sweeping units
+ * b, b + grid, ... (a static assignment, like a grid-stride loop over
+ * tracks; with FP32 boundary storage only, else one workgroup per unit).
+ * Applies to the FP32 per-lane sweep; drops any store.  EINVAL for other
+ * values. */
+MOC_API int moc_solver_set_schedule(moc_solver *s, int order, int persistent);
 
 /* Eigenvalue mode: power iteration on k-eff (the multiplication factor the
  * paper's validation reports, Table 2).  nu_sigma_f and chi are [M][G]

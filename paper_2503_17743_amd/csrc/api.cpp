@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <new>
 #include <string>
@@ -186,6 +187,35 @@ int moc_solver_set_walk(moc_solver *sv, int walk) {
     if (!sv) return fail(MOC_EINVAL, "NULL solver");
     if (walk < 0 || walk > 2) return fail(MOC_EINVAL, "walk must be 0 (automatic), 1 (lockstep) or 2 (per-lane)");
     sv->s.set_walk(walk);
+    return MOC_OK;
+}
+
+int moc_solver_store_segments(moc_solver *sv, void *dev_store, size_t store_bytes, moc_store_info *info) {
+    if (!sv) return fail(MOC_EINVAL, "NULL solver");
+    if (dev_store && (reinterpret_cast<uintptr_t>(dev_store) & 255) != 0)
+        return fail(MOC_EINVAL, "store must be 256-byte aligned");
+    return sv->s.store_segments(static_cast<char *>(dev_store), dev_store ? store_bytes : 0, info);
+}
+
+int moc_solver_set_schedule(moc_solver *sv, int order, int persistent) {
+    if (!sv) return fail(MOC_EINVAL, "NULL solver");
+    if (order < 0 || order > 2) return fail(MOC_EINVAL, "order must be 0, 1 or 2");
+    if (persistent != 0 && persistent != 1) return fail(MOC_EINVAL, "persistent must be 0 or 1");
+    return sv->s.set_schedule(order, persistent);
+}
+
+int moc_solver_set_window(moc_solver *sv, int threads) {
+    if (!sv) return fail(MOC_EINVAL, "NULL solver");
+    if (threads != 0 && threads != 256 && threads != 512 && threads != 1024)
+        return fail(MOC_EINVAL, "threads must be 0 (automatic), 256, 512 or 1024");
+    if (sv->s.set_window(threads)) return fail(MOC_EINVAL, "no window of that workgroup size fits the LDS");
+    return MOC_OK;
+}
+
+int moc_solver_window(const moc_solver *sv, int *threads, int *segments) {
+    if (!sv) return fail(MOC_EINVAL, "NULL solver");
+    if (threads) *threads = sv->s.lane_nt;
+    if (segments) *segments = sv->s.lane_win;
     return MOC_OK;
 }
 

@@ -34,6 +34,15 @@ struct SweepArgs {
     int mode;                                     // 0 sweep, 1 volume tally
 };
 
+// One recorded piece of the stored-segment (EXP) sweep: the LDS tally /
+// reduced-source row of the piece (bits 0-15) and its 2D segment in the window
+// (bits 16-31), and its 3D length (FP32; 0 for a piece below the minimum
+// length, -1 for a lane whose line has left the window).
+struct Piece {
+    unsigned idx;
+    float len;
+};
+
 struct WinArgs {
     SweepArgs s;
     const int *work;          // work unit codes 2*t + dir (longest first)
@@ -43,6 +52,14 @@ struct WinArgs {
     int lstride;              // line stride inside a bundle (1: consecutive lines)
     int walk;                 // transport walk of the FP32 one-chunk sweep: 0 lockstep, 1 per-lane
     int small_wg;             // per-lane walk in 256-thread workgroups (Sw sized for them)
+    int big_wg;               // per-lane walk in 1024-thread workgroups (Sw sized for them)
+    int persist_units;        // > 0: persistent grid, workgroup b sweeps units b, b + grid, ...
+    // stored-segment (EXP) sweep of the per-lane walk
+    int exp_pass;             // store pass: 1 count, 2 step table, 3 record
+    unsigned long long *exp_count;   // count pass: [launch unit][2] = {wave steps, bundle windows}
+    const unsigned *exp_tbase;       // first step-table entry of each unit of the launch
+    unsigned *exp_table;             // per (unit, window, bundle): steps, then their exclusive prefix
+    Piece *exp_data;                 // recorded pieces [wave step][64 lanes]
 };
 
 // Per-problem control of a batched step: the stopping rule and the state the

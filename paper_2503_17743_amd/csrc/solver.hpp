@@ -6,13 +6,13 @@
 #include <string>
 #include <vector>
 
+#include "args.hpp"
 #include "plan.hpp"
 
 namespace moc {
 
 struct SweepArgs;
 struct FsrArgs;
-struct WinArgs;
 struct SlotCtl;
 
 // One batched source iteration of several problems (serving): device tables
@@ -60,12 +60,18 @@ struct Solver {
     int lstride = 1;                 // windowed sweep: line stride inside a bundle
     int walk = 0;                    // transport walk in use: 0 lockstep, 1 per-lane
     int walk_auto = 0;               // the plan's choice (set at upload)
+    int sw256 = 0, sw1024 = 0;       // per-lane walk: windows of 256 / 1024-thread workgroups
+    int window_nt = 0;               // workgroup size the caller chose (0: automatic)
+    int lane_nt = 512, lane_win = 0; // the single solver's per-lane sweep: workgroup size, window
+    void choose_lane_window();
+    int set_window(int threads);
     int lane_sw = 0;                 // per-lane walk: 2D segments per window of a 256-thread
                                      // workgroup (0: such windows are too short, 512 threads)
     void set_walk(int mode) { walk = mode == 0 ? walk_auto : mode - 1; }
     std::vector<long long> chunk_off, trk_off;
     std::vector<int> work_host;      // windowed-sweep work list (longest first)
     std::vector<float> work_cost;    // estimated cost of each work-list unit
+    std::vector<double> track_work;  // estimated work per 2D track (lines x 2D segments)
     std::vector<int> cnt;
 
     // bind to a workspace: layout, upload, volumes, reset (returns moc_status)
@@ -76,6 +82,30 @@ struct Solver {
     int compute_volumes();
     void launch_sweep(SweepArgs a, bool fp64, const int *units = nullptr, int n_units = 0,
                       const int *filt_n = nullptr, const long long *filt_i0 = nullptr);
+    bool lane_path(const SweepArgs &a, bool fp64) const;   // the per-lane FP32 transport sweep
+    WinArgs lane_args(const SweepArgs &a) const;
+    int resident_workgroups() const;
+    // schedule of the work units (paper section 4.3): order 0 longest first,
+    // 1 natural (2D track order), 2 by decreasing work in groups of the
+    // resident workgroup count, every other group reversed; persistent: a
+    // grid of resident workgroups, each sweeping units b, b + grid, ...
+    int order = 0;
+    int persistent = 0;
+    int set_schedule(int order, int persistent);
+    int upload_work_list();
+    // stored-segment (EXP) sweep (paper section 4.2): the recorded pieces of
+    // the units with the most pieces, replayed; the other units on the fly
+    int exp_units = 0, otf_units = 0;
+    int *d_exp_work = nullptr, *d_otf_work = nullptr;
+    unsigned *d_exp_tbase = nullptr, *d_exp_table = nullptr;
+    Piece *d_exp_data = nullptr;
+    int store_segments(char *buf, size_t bytes, moc_store_info *out);
+    void drop_store() {
+        exp_units = otf_units = 0;
+        d_exp_work = d_otf_work = nullptr;
+        d_exp_tbase = d_exp_table = nullptr;
+        d_exp_data = nullptr;
+    }
     int window_size(bool fp64) const { return fp64 ? sw64 : sw32; }
     WinArgs win_args_batched() const;   // descriptor of the batched sweep (even orientation)
     size_t win_lds() const;

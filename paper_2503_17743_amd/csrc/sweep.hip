@@ -45,6 +45,14 @@ constexpr int kWinDeepBelow = 8;
 // (four per CU), used when such a window still holds kWinSmallMinSw segments
 constexpr size_t kWinLdsBudgetSmall = 40 * 1024;
 constexpr int kWinSmallMinSw = 16;
+// Per-lane walk on deep stacks: 1024-thread workgroups (one per CU, the same
+// 16 waves per CU) with windows of up to 156 KB, used when the 512-thread
+// window holds fewer than kWinBigBelow segments and the large one at least
+// twice as many: fewer windows per line, so fewer carries of a line's flux
+// between windows and fewer per-line set-ups
+constexpr int kWinThreadsBig = 1024;
+constexpr size_t kWinLdsBudgetBig = 156 * 1024;
+constexpr int kWinBigBelow = 16;
 constexpr int kSlots = 64;        // spread of the scalar accumulators
 constexpr size_t kScalBytes = 128 * 1024;   // scalar block of a workspace
 constexpr int kSlotStride = 16;   // doubles between slots (separate cache lines)
@@ -431,6 +439,17 @@ __host__ __device__ inline size_t win_lds_bytes(int Sw, int K, int G, int rbytes
 }
 
 
+// floor(a / b) for 0 <= a < 2^20 and 1 <= b: the float estimate a * (1/b)
+// (hardware reciprocal) is within one of the quotient, and one correction
+// step in integers makes it exact
+__device__ inline int div_small(int a, int b) {
+    int q = (int)((float)a * __builtin_amdgcn_rcpf((float)b));
+    const int r = a - q * b;
+    q += (r >= b) ? 1 : 0;
+    q -= (r < 0) ? 1 : 0;
+    return q;
+}
+
 __device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ inline float uniform_val(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
@@ -450,11 +469,19 @@ __device__ inline double uniform_val(double v) {
 // moves on to its next 2D segment by itself (reading that segment's Sigma_t
 // row from LDS), instead of the whole wave taking every 2D segment together.
 // Both walks give every line the same pieces in the same order.
+// EXP (per-lane walk only): 0 on-the-fly sweep; 1 store pass of the
+// stored-segment sweep (wa.exp_pass: 1 count the wave steps and bundle windows
+// of each unit, 2 write each bundle window's step count to the step table,
+// 3 record every lane's pieces), which walks the geometry only; 2 replay: the
+// transport sweep reads the recorded pieces instead of walking the geometry.
 template <typename R, typename B, int MODE, int EXPM, bool BWD, bool C1, int GC = 0, bool LANE = false,
-          int NT = kWinThreads>
+          int NT = kWinThreads, int EXP = 0>
 __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit,
                                            unsigned char *smem, bool flip = false) {
     static_assert(!LANE || (MODE == 0 && C1), "the per-lane walk is the one-chunk transport sweep");
+    static_assert(EXP == 0 || LANE, "the stored-segment sweep records the per-lane walk");
+    // the transport arithmetic runs in the on-the-fly sweep and in the replay
+    constexpr bool kPhys = EXP != 1;
     const SweepArgs &a = wa.s;
     // boundary buffers of this sweep (flip: the descriptor's pair swapped)
     void *const psi_in = flip ? a.psi_out : a.psi_in;
@@ -480,6 +507,11 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
     int *r_hi = r_lo + kMaxPolar;
     int *r_st = r_hi + kMaxPolar;       // line stride of each stack's bundles
     int *bpre = r_st + kMaxPolar;
+    // per-lane walk: complete blocks of each stack's bundles, and the lines
+    // per bundle (q or q + 1, the first x bundles longer) of its last block
+    int *r_full = bpre + kMaxPolar + 1;
+    int *r_q = r_full + kMaxPolar;
+    int *r_x = r_q + kMaxPolar;
     // FP32 stable attenuation: Sigma_t is staged times log2(e), so that
     // Sigma_t l is the exponent of 2 itself
     constexpr bool kL2 = std::is_same<R, float>::value && EXPM == 0 && MODE == 0;
@@ -504,6 +536,11 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
 
     double s_in = 0.0, s_out = 0.0, leak = 0.0;
     long long nseg = 0, link_err = 0;
+    // stored-segment sweep: step-table entry of the current window's first
+    // bundle (every bundle window of the unit in sweep order), and the count
+    // pass's totals of this wave
+    unsigned bw_run = (EXP != 0 && wa.exp_tbase) ? wa.exp_tbase[unit] : 0u;
+    unsigned long long exp_steps = 0;
 
     for (int wi = 0; wi < nwin; ++wi) {
         const int w = dir ? nwin - 1 - wi : wi;
@@ -518,7 +555,7 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
             s_reg[i] = a.seg_reg[k0 + i];
         }
         if (tid == 0) s_pos[nsw] = wb_;
-        if (MODE == 0) {
+        if (MODE == 0 && kPhys) {
             for (int i = tid; i < nsw * G; i += NT) {
                 const int kk = i / G;
                 const int m = a.reg_mat[a.seg_reg[k0 + kk]] * G + (i - kk * G);
@@ -573,13 +610,17 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
             // The per-lane walk packs the lines of all stacks into bundles
             // instead (the prefix then counts lines): lanes need no common
             // polar angle there, and the stacks' partial bundles merge.
-            int nb = 0, S = 1;
+            int nb = 0, S = 1, full = 0, q = 0, x = 0;
             if (hi >= lo) {
                 const int nl = hi - lo + 1;
                 S = min(Smax, (nl + T - 1) / T);
                 const int ST = S * T;
                 const int blocks = (nl + ST - 1) / ST;
                 nb = LANE ? nl : (blocks - 1) * S + min(S, nl - (blocks - 1) * ST);
+                full = (nl - 1) / ST;
+                const int rem = nl - full * ST;
+                q = rem / S;
+                x = rem - q * S;
             }
             int sc = nb;
             for (int o = 1; o < 64; o <<= 1) {
@@ -591,6 +632,11 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
             r_st[lane] = S;
             bpre[lane + 1] = sc;
             if (lane == 0) bpre[0] = 0;
+            if (LANE) {
+                r_full[lane] = full;
+                r_q[lane] = q;
+                r_x[lane] = x;
+            }
         }
         __syncthreads();
         const int n_lines = bpre[P];     // per-lane walk: lines of all stacks
@@ -602,29 +648,31 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                 // entry g of the window's packed list: stack n, and its line
                 // in the order of the strided bundles above (those bundles
                 // concatenated), so neighbouring lanes stay S lines apart
-                const int g = bnd * T + tr;
+                // (T = 64 lines per bundle here: one chunk of groups per lane)
+                const int g = bnd * 64 + tr;
                 const int gg = min(g, n_lines - 1);
                 while (bpre[n + 1] <= gg) ++n;
-                const int lo = r_lo[n], nl = r_hi[n] - lo + 1, S = r_st[n];
-                const int ST = S * T, full = (nl - 1) / ST;     // complete blocks
+                const int lo = r_lo[n], S = r_st[n];
+                const int ST = S * 64, full = r_full[n];        // complete blocks
                 const int p = gg - bpre[n];
-                const int b = min(p / ST, full);
+                const int b = min(div_small(p, ST), full);
                 const int within = p - b * ST;
                 int r, k;
                 if (b < full) {
-                    r = within / T;
-                    k = within - r * T;
+                    r = within >> 6;
+                    k = within & 63;
                 } else {
-                    // last block: rem lines in min(S, rem) bundles, the first
-                    // x of them one line longer
-                    const int rem = nl - full * ST, q = rem / S, x = rem - q * S;
+                    // last block: its lines in min(S, lines) bundles of q or
+                    // q + 1 lines, the first x of them one line longer
+                    const int q = r_q[n], x = r_x[n];
                     if (within < x * (q + 1)) {
-                        r = within / (q + 1);
+                        r = div_small(within, q + 1);
                         k = within - r * (q + 1);
                     } else {
                         const int w2 = within - x * (q + 1);
-                        r = x + w2 / q;
-                        k = w2 - (w2 / q) * q;
+                        const int r2 = div_small(w2, q);
+                        r = x + r2;
+                        k = w2 - r2 * q;
                     }
                 }
                 i = lo + b * ST + r + S * k;
@@ -688,7 +736,7 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
             // the lane carries W * psi along its line: then W * delta_psi is
             // what Eq. 3 yields directly, and the tally needs no multiply
             const R Wr = (R)W;
-            if (MODE == 0 && active) {
+            if (MODE == 0 && kPhys && active) {
                 const B *pin = (const B *)psi_in + slot * G + g0;
                 if (!starts) {
                     // carried from the previous window (already scaled by W)
@@ -724,7 +772,52 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
             };
-            if constexpr (LANE) {
+            if constexpr (LANE && EXP == 2) {
+                // replay of the recorded pieces of this bundle window: the
+                // same transport arithmetic as the per-lane walk below, with
+                // each step's piece read instead of generated
+                const unsigned off = wa.exp_table[bw_run + bnd];
+                const int nst = (int)(wa.exp_table[bw_run + bnd + 1] - off);
+                const Piece *src = wa.exp_data + (size_t)off * 64 + lane;
+                // the pieces of the next kReplayAhead steps are in flight while
+                // this step computes (HBM latency spans several steps)
+                constexpr int kReplayAhead = 4;
+                const Piece none{0u, -1.0f};
+                Piece ahead[kReplayAhead];
+#pragma unroll
+                for (int d = 0; d < kReplayAhead; ++d) ahead[d] = d < nst ? src[(size_t)d * 64] : none;
+                for (int step = 0; step < nst; ++step) {
+                    const Piece cur = ahead[0];
+#pragma unroll
+                    for (int d = 0; d + 1 < kReplayAhead; ++d) ahead[d] = ahead[d + 1];
+                    ahead[kReplayAhead - 1] =
+                        step + kReplayAhead < nst ? src[(size_t)(step + kReplayAhead) * 64] : none;
+                    if (cur.len >= 0.0f) {
+                        const int li = (int)(cur.idx & 0xffffu);
+                        const int lst = (int)__umul24(cur.idx >> 16, (unsigned)G);
+                        const R lr = (R)cur.len;
+                        R qv[kGL], stv[kGL];
+#pragma unroll
+                        for (int j = 0; j < kGL; ++j)
+                            if (j < GL) {
+                                qv[j] = q_l[li + j];
+                                stv[j] = s_st[lst + j];
+                            }
+                        flush_pending();
+#pragma unroll
+                        for (int j = 0; j < kGL; ++j)
+                            if (j < GL) {
+                                const R f = kL2 ? (R)one_minus_exp2_f32((float)(stv[j] * lr))
+                                                : one_minus_exp<R>(stv[j] * lr, EXPM);
+                                const R d = fma(-Wr, qv[j], psi[j]) * f;
+                                psi[j] -= d;
+                                pend[j] = d;
+                            }
+                        pend_li = li;
+                        nseg += cur.len > 0.0f;
+                    }
+                }
+            } else if constexpr (LANE) {
                 // the lane's first 2D segment: the one holding its start in
                 // sweep order (inside [ka, kb], since its extent is inside the
                 // bundle's)
@@ -751,8 +844,13 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                 // at most (segments) + K + 2 pieces in the window: a bound on
                 // the steps that the walk never reaches
                 const int max_steps = 64 * (kb - ka + 1 + K + 2) + 8;
+                // store pass: this bundle window's first recorded wave step
+                const unsigned rec_off = (EXP == 1 && wa.exp_pass == 3) ? wa.exp_table[bw_run + bnd] : 0u;
+                int steps_done = 0;
                 for (int step = 0; step < max_steps; ++step) {
                     if (__ballot(!fin) == 0) break;
+                    ++steps_done;
+                    Piece rec{0u, -1.0f};
                     if (!fin) {
                         const bool cross = dir ? (wk.lnp > e) : (wk.lnp < e);
                         const double lend = cross ? wk.lnp : e;
@@ -761,6 +859,10 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                         const int kz = min(max(wk.k, 0), K - 1);
                         const int li = lq + (int)__umul24((unsigned)kz, (unsigned)G);
                         const R lr = valid ? (R)l3 : (R)0;
+                        if constexpr (EXP == 1) {
+                            rec.idx = (unsigned)li | ((unsigned)sg << 16);
+                            rec.len = (float)lr;
+                        } else {
                         R qv[kGL], stv[kGL];
 #pragma unroll
                         for (int j = 0; j < kGL; ++j)
@@ -779,6 +881,7 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                                 pend[j] = d;
                             }
                         pend_li = li;
+                        }
                         nseg += valid;
                         wk.lcur = lend;
                         if (cross) {
@@ -795,6 +898,12 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                             e = dir ? (sp > ls ? sp : ls) : (sp < le ? sp : le);
                         }
                     }
+                    if constexpr (EXP == 1)
+                        if (wa.exp_pass == 3) wa.exp_data[((size_t)rec_off + step) * 64 + lane] = rec;
+                }
+                if constexpr (EXP == 1) {
+                    if (wa.exp_pass == 2 && lane == 0) wa.exp_table[bw_run + bnd] = (unsigned)steps_done;
+                    exp_steps += (unsigned long long)steps_done;
                 }
             } else {
             const int nk = kb - ka + 1;
@@ -846,7 +955,7 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
             }
             }
             flush_pending();
-            if (MODE == 0 && active) {
+            if (MODE == 0 && kPhys && active) {
                 if (!ends) {
                     B *pc = (B *)psi_in + slot * G + g0;            // carried to the next window
 #pragma unroll
@@ -883,9 +992,12 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
             }
         }
         __syncthreads();
+        if constexpr (EXP == 1)
+            if (wa.exp_pass == 1 && tid == 0) atomicAdd(&wa.exp_count[2 * (size_t)unit + 1], (unsigned long long)total);
+        bw_run += (unsigned)total;
         // flush the window tally: one HBM atomic per touched FSR-group (the
         // volume tally has one entry per FSR, kept in the g = 0 slots)
-        for (int i = tid; i < nsw * KG; i += NT) {
+        for (int i = tid; i < nsw * KG && kPhys; i += NT) {
             const double v = acc_l[i];
             if (v != 0.0) {
                 const int kk = i / KG;
@@ -897,6 +1009,11 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
             }
         }
         __syncthreads();
+    }
+    if constexpr (EXP == 1) {
+        // store pass: the count pass adds this wave's steps to its unit
+        if (wa.exp_pass == 1 && lane == 0) atomicAdd(&wa.exp_count[2 * (size_t)unit], exp_steps);
+        return;
     }
     // per-wave totals -> spread scalar slots
     const double v_in = wave_sum(s_in), v_out = wave_sum(s_out), v_lk = wave_sum(leak);
@@ -927,26 +1044,48 @@ __global__ __launch_bounds__(kWinThreads) __attribute__((amdgpu_waves_per_eu(4))
 
 // The FP32 transport sweep with the per-lane walk (one-chunk lanes, G = GC).
 // NT threads per workgroup (512, or 256 with the shorter windows of shallow
-// stacks: fewer waves wait at each window's barrier).
-template <typename B, int GC, int NT>
+// stacks: fewer waves wait at each window's barrier).  EXP 0: the on-the-fly
+// sweep; EXP 2: the replay of recorded pieces (stored-segment sweep).  With
+// wa.persist_units > 0 the grid is persistent: workgroup b sweeps the units
+// b, b + gridDim.x, ... of the work list (a static assignment, as in a
+// grid-stride loop over tracks); otherwise one workgroup per unit.
+template <typename B, int GC, int NT, int EXP = 0, bool PERSIST = false>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_win_lane(WinArgs wa) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int code = wa.work[blockIdx.x];
-    if (code & 1) sweep_unit<float, B, 0, 0, true, true, GC, true, NT>(wa, code, blockIdx.x, smem);
-    else sweep_unit<float, B, 0, 0, false, true, GC, true, NT>(wa, code, blockIdx.x, smem);
+    if constexpr (PERSIST) {
+        for (int u = blockIdx.x; u < wa.persist_units; u += gridDim.x) {
+            const int code = wa.work[u];
+            if (code & 1) sweep_unit<float, B, 0, 0, true, true, GC, true, NT, EXP>(wa, code, u, smem);
+            else sweep_unit<float, B, 0, 0, false, true, GC, true, NT, EXP>(wa, code, u, smem);
+        }
+    } else {
+        const int code = wa.work[blockIdx.x];
+        if (code & 1) sweep_unit<float, B, 0, 0, true, true, GC, true, NT, EXP>(wa, code, blockIdx.x, smem);
+        else sweep_unit<float, B, 0, 0, false, true, GC, true, NT, EXP>(wa, code, blockIdx.x, smem);
+    }
 }
 
-template <typename B, int NT>
+// Store pass of the stored-segment sweep (wa.exp_pass 1 count, 2 step table,
+// 3 record): the per-lane walk's geometry only, for any G <= 8.
+template <int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_win_store(WinArgs wa) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int code = wa.work[blockIdx.x];
+    if (code & 1) sweep_unit<float, float, 0, 0, true, true, 0, true, NT, 1>(wa, code, blockIdx.x, smem);
+    else sweep_unit<float, float, 0, 0, false, true, 0, true, NT, 1>(wa, code, blockIdx.x, smem);
+}
+
+template <typename B, int NT, int EXP = 0, bool PERSIST = false>
 static void launch_lane(const WinArgs &wa, unsigned nb, size_t lds, hipStream_t st) {
     switch (wa.s.G) {
-    case 1: k_sweep_win_lane<B, 1, NT><<<nb, NT, lds, st>>>(wa); break;
-    case 2: k_sweep_win_lane<B, 2, NT><<<nb, NT, lds, st>>>(wa); break;
-    case 3: k_sweep_win_lane<B, 3, NT><<<nb, NT, lds, st>>>(wa); break;
-    case 4: k_sweep_win_lane<B, 4, NT><<<nb, NT, lds, st>>>(wa); break;
-    case 5: k_sweep_win_lane<B, 5, NT><<<nb, NT, lds, st>>>(wa); break;
-    case 6: k_sweep_win_lane<B, 6, NT><<<nb, NT, lds, st>>>(wa); break;
-    case 7: k_sweep_win_lane<B, 7, NT><<<nb, NT, lds, st>>>(wa); break;
-    default: k_sweep_win_lane<B, 8, NT><<<nb, NT, lds, st>>>(wa); break;
+    case 1: k_sweep_win_lane<B, 1, NT, EXP, PERSIST><<<nb, NT, lds, st>>>(wa); break;
+    case 2: k_sweep_win_lane<B, 2, NT, EXP, PERSIST><<<nb, NT, lds, st>>>(wa); break;
+    case 3: k_sweep_win_lane<B, 3, NT, EXP, PERSIST><<<nb, NT, lds, st>>>(wa); break;
+    case 4: k_sweep_win_lane<B, 4, NT, EXP, PERSIST><<<nb, NT, lds, st>>>(wa); break;
+    case 5: k_sweep_win_lane<B, 5, NT, EXP, PERSIST><<<nb, NT, lds, st>>>(wa); break;
+    case 6: k_sweep_win_lane<B, 6, NT, EXP, PERSIST><<<nb, NT, lds, st>>>(wa); break;
+    case 7: k_sweep_win_lane<B, 7, NT, EXP, PERSIST><<<nb, NT, lds, st>>>(wa); break;
+    default: k_sweep_win_lane<B, 8, NT, EXP, PERSIST><<<nb, NT, lds, st>>>(wa); break;
     }
 }
 
@@ -1532,8 +1671,13 @@ int Solver::upload(const Plan &p) {
             max_seg = std::max<int>(max_seg, (int)(p.seg_first[t + 1] - p.seg_first[t]));
         int s = 0;
         while (s < max_seg && win_lds_bytes(s + 1, p.K, p.G, 4) <= kWinLdsBudgetSmall) ++s;
+        sw256 = s;
         if (s >= kWinSmallMinSw || (s >= 1 && s == max_seg)) lane_sw = s;
+        int b = 0;
+        while (b < max_seg && win_lds_bytes(b + 1, p.K, p.G, 4) <= kWinLdsBudgetBig) ++b;
+        sw1024 = b;
     }
+    choose_lane_window();
     std::vector<std::pair<double, int>> est(p.n2d);
     for (int64_t t = 0; t < p.n2d; ++t) {
         double lines = 0;
@@ -1554,6 +1698,8 @@ int Solver::upload(const Plan &p) {
     }
     HIPCHK(put(lay.off_work, work.data(), work.size() * 4));
     work_host = work;
+    track_work.resize(p.n2d);
+    for (int64_t t = 0; t < p.n2d; ++t) track_work[est[t].second] = est[t].first;
     chunk_off.assign(p.chunk_off.begin(), p.chunk_off.end());
     trk_off.assign(p.trk_off.begin(), p.trk_off.end());
     cnt.assign(p.cnt.begin(), p.cnt.end());
@@ -1587,6 +1733,7 @@ static void launch_win_c(const WinArgs &wa, unsigned nb, size_t lds, hipStream_t
         k_sweep_win<B, 1, 0, C1><<<nb, kWinThreads, lds, st>>>(wa);
     } else if (expm == 0 && C1 && wa.walk == 1) {
         if (wa.small_wg) launch_lane<B, 256>(wa, nb, lds, st);
+        else if (wa.big_wg) launch_lane<B, kWinThreadsBig>(wa, nb, lds, st);
         else launch_lane<B, kWinThreads>(wa, nb, lds, st);
     } else if (expm == 0) {
         // the transport sweep with the group count compiled in (G <= 8)
@@ -1612,16 +1759,138 @@ static void launch_win(const WinArgs &wa, unsigned nb, size_t lds, hipStream_t s
     else launch_win_c<R, B, false>(wa, nb, lds, st, mode, expm);
 }
 
+// The per-lane FP32 transport sweep of a work list (replay or on-the-fly),
+// one workgroup per unit or a persistent grid of at most `grid` workgroups.
+template <int EXP>
+static void launch_lane_list(WinArgs wa, int n, int grid, size_t lds, bool psi64, hipStream_t st) {
+    if (n <= 0) return;
+    if (grid > 0 && !psi64) {
+        // persistent grid (FP32 boundary storage only)
+        wa.persist_units = n;
+        const unsigned nb = (unsigned)std::min(n, grid);
+        if (wa.small_wg) launch_lane<float, 256, EXP, true>(wa, nb, lds, st);
+        else if (wa.big_wg) launch_lane<float, kWinThreadsBig, EXP, true>(wa, nb, lds, st);
+        else launch_lane<float, kWinThreads, EXP, true>(wa, nb, lds, st);
+        return;
+    }
+    const unsigned nb = (unsigned)n;
+    wa.persist_units = 0;
+    if (psi64) {
+        if (wa.small_wg) launch_lane<double, 256, EXP>(wa, nb, lds, st);
+        else if (wa.big_wg) launch_lane<double, kWinThreadsBig, EXP>(wa, nb, lds, st);
+        else launch_lane<double, kWinThreads, EXP>(wa, nb, lds, st);
+    } else {
+        if (wa.small_wg) launch_lane<float, 256, EXP>(wa, nb, lds, st);
+        else if (wa.big_wg) launch_lane<float, kWinThreadsBig, EXP>(wa, nb, lds, st);
+        else launch_lane<float, kWinThreads, EXP>(wa, nb, lds, st);
+    }
+}
+
+// Store pass launch over n units with the lane sweep's workgroup size.
+static void launch_store(const WinArgs &wa, int n, size_t lds, hipStream_t st) {
+    if (wa.small_wg) k_sweep_win_store<256><<<n, 256, lds, st>>>(wa);
+    else if (wa.big_wg) k_sweep_win_store<kWinThreadsBig><<<n, kWinThreadsBig, lds, st>>>(wa);
+    else k_sweep_win_store<kWinThreads><<<n, kWinThreads, lds, st>>>(wa);
+}
+
+bool Solver::lane_path(const SweepArgs &a, bool fp64) const {
+    return !fp64 && a.mode == 0 && a.exp_mode == 0 && walk == 1 && group_chunks(info.n_groups) == 1 &&
+           lane_win >= 1;
+}
+
+WinArgs Solver::lane_args(const SweepArgs &a) const {
+    WinArgs wa;
+    std::memset(&wa, 0, sizeof(wa));
+    wa.s = a;
+    wa.small_wg = lane_nt == 256 ? 1 : 0;
+    wa.big_wg = lane_nt == kWinThreadsBig ? 1 : 0;
+    wa.Sw = lane_win;
+    wa.lstride = lstride;
+    wa.walk = walk;
+    return wa;
+}
+
+// Workgroup size and window of the single solver's per-lane sweep: 256
+// threads on shallow stacks (the 40 KB window holds kWinSmallMinSw segments,
+// or a whole track), 1024 threads on deep ones (the 512-thread window holds
+// fewer than kWinBigBelow segments and the 156 KB one at least twice as
+// many), else 512; or the size the caller chose (moc_solver_set_window).
+void Solver::choose_lane_window() {
+    lane_nt = kWinThreads;
+    lane_win = sw32;
+    if (group_chunks(info.n_groups) != 1) return;
+    if (window_nt == 256 && sw256 >= 1) {
+        lane_nt = 256;
+        lane_win = sw256;
+    } else if (window_nt == kWinThreadsBig && sw1024 >= 1) {
+        lane_nt = kWinThreadsBig;
+        lane_win = sw1024;
+    } else if (window_nt == 0) {
+        if (lane_sw >= 1) {
+            lane_nt = 256;
+            lane_win = lane_sw;
+        } else if (sw32 >= 1 && sw32 < kWinBigBelow && sw1024 >= 2 * sw32) {
+            lane_nt = kWinThreadsBig;
+            lane_win = sw1024;
+        }
+    }
+}
+
+int Solver::set_window(int threads) {
+    if (threads == 256 && sw256 < 1) return MOC_EINVAL;
+    if (threads == kWinThreadsBig && sw1024 < 1) return MOC_EINVAL;
+    window_nt = threads;
+    choose_lane_window();
+    drop_store();
+    drop_step_graphs();
+    return MOC_OK;
+}
+
+// Workgroups of the lane sweep resident on the device at once: the LDS of a
+// workgroup and 16 waves per CU (amdgpu_waves_per_eu(4) on 4 SIMDs).
+int Solver::resident_workgroups() const {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const size_t lds = win_lds_bytes(std::max(lane_win, 1), K, info.n_groups, 4);
+    const int by_lds = (int)std::max<size_t>(1, (160 * 1024) / std::max<size_t>(lds, 1));
+    const int by_waves = std::max(1, 16 / (lane_nt / 64));
+    return cus * std::min(by_lds, by_waves);
+}
+
 void Solver::launch_sweep(SweepArgs a, bool fp64, const int *units, int n_units,
                           const int *filt_n, const long long *filt_i0) {
     int sw = window_size(fp64);
-    // the per-lane walk of shallow stacks runs in 256-thread workgroups
-    const bool small_wg = !fp64 && a.mode == 0 && a.exp_mode == 0 && walk == 1 && lane_sw >= 1;
-    if (small_wg) sw = lane_sw;
+    // the per-lane walk runs in its own workgroup size and window
+    const bool lane = !fp64 && a.mode == 0 && a.exp_mode == 0 && walk == 1 && lane_win >= 1;
+    if (lane) sw = lane_win;
+    if (!units && lane_path(a, fp64) && (exp_units > 0 || persistent)) {
+        // stored-segment sweep: the stored units replayed, then the rest on
+        // the fly (two launches in order on the stream); or a persistent grid
+        WinArgs wa = lane_args(a);
+        const size_t lds = win_lds_bytes(wa.Sw, K, info.n_groups, 4);
+        const int grid = persistent ? resident_workgroups() : 0;
+        if (exp_units > 0) {
+            WinArgs wr = wa;
+            wr.work = d_exp_work;
+            wr.exp_tbase = d_exp_tbase;
+            wr.exp_table = d_exp_table;
+            wr.exp_data = d_exp_data;
+            launch_lane_list<2>(wr, exp_units, grid, lds, lay.psi64, stream);
+            wa.work = d_otf_work;
+            launch_lane_list<0>(wa, otf_units, grid, lds, lay.psi64, stream);
+        } else {
+            wa.work = ws_ptr<int>(ws, lay.off_work);
+            launch_lane_list<0>(wa, (int)(2 * info.n_2d_tracks), grid, lds, lay.psi64, stream);
+        }
+        return;
+    }
     if (sw >= 1) {
         WinArgs wa;
+        std::memset(&wa, 0, sizeof(wa));
         wa.s = a;
-        wa.small_wg = small_wg ? 1 : 0;
+        wa.small_wg = (lane && lane_nt == 256) ? 1 : 0;
+        wa.big_wg = (lane && lane_nt == kWinThreadsBig) ? 1 : 0;
         wa.work = units ? units : ws_ptr<int>(ws, lay.off_work);
         wa.filt_n = filt_n;
         wa.filt_i0 = filt_i0;
@@ -1652,6 +1921,188 @@ void Solver::launch_sweep(SweepArgs a, bool fp64, const int *units, int n_units,
         if (fp64) k_sweep<double, float><<<grid, 256, 0, stream>>>(a);
         else k_sweep<float, float><<<grid, 256, 0, stream>>>(a);
     }
+}
+
+// Work units (2 per 2D track) in the order of the schedule.
+static std::vector<int> ordered_units(const std::vector<double> &track_work, int order, int group) {
+    const int64_t n2d = (int64_t)track_work.size();
+    std::vector<int> codes(2 * n2d);
+    for (int64_t i = 0; i < 2 * n2d; ++i) codes[i] = (int)i;
+    if (order == 1) return codes;     // natural: 2D track order (Eq. 13), both directions
+    std::stable_sort(codes.begin(), codes.end(), [&](int x, int y) {
+        return track_work[x >> 1] > track_work[y >> 1];
+    });
+    if (order == 2 && group > 0) {
+        // groups of `group` units by decreasing work, every other group reversed
+        for (int64_t g0 = group, k = 1; g0 < 2 * n2d; g0 += group, ++k)
+            if (k & 1) std::reverse(codes.begin() + g0, codes.begin() + std::min<int64_t>(g0 + group, 2 * n2d));
+    }
+    return codes;
+}
+
+int Solver::upload_work_list() {
+    const std::vector<int> codes = ordered_units(track_work, order, resident_workgroups());
+    HIPCHK(hipMemcpyAsync(ws + lay.off_work, codes.data(), codes.size() * 4, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    return MOC_OK;
+}
+
+int Solver::set_schedule(int ord, int pers) {
+    order = ord;
+    persistent = pers;
+    drop_store();          // the store's lists follow the order: store again
+    drop_step_graphs();
+    return upload_work_list();
+}
+
+// Stored-segment sweep (paper section 4.2).  A count pass walks every unit's
+// geometry once and gives its wave steps and bundle windows; the units with
+// the largest footprint are taken, in decreasing order, while they fit the
+// caller's buffer; a table pass writes the step count of each of their bundle
+// windows, whose exclusive prefix gives each window's place in the store; a
+// record pass writes every lane's pieces there.  Buffer layout (256-byte
+// aligned parts): stored unit codes, remaining unit codes, table base per
+// stored unit, step table (+1 terminal entry), pieces [wave step][64 lanes].
+int Solver::store_segments(char *buf, size_t bytes, moc_store_info *out) {
+    drop_store();
+    drop_step_graphs();
+    moc_store_info inf{};
+    const int n_units = (int)(2 * info.n_2d_tracks);
+    inf.units_total = n_units;
+    if (out) *out = inf;
+    if (!buf || bytes == 0) return MOC_OK;
+    SweepArgs a = sweep_args(0, 0);
+    if (!lane_path(a, false)) {
+        set_error("the stored-segment sweep records the per-lane FP32 walk (G <= 8, windowed sweep)");
+        return MOC_EINVAL;
+    }
+    WinArgs wa = lane_args(a);
+    if ((size_t)wa.Sw * K * info.n_groups >= 65536 || wa.Sw >= 65536) {
+        set_error("window too large for the 16-bit piece indices of the store");
+        return MOC_EINVAL;
+    }
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t lds = win_lds_bytes(wa.Sw, K, info.n_groups, 4);
+    // ---- count pass over every unit (in the schedule's order)
+    const size_t cnt_bytes = al((size_t)n_units * 16);
+    if (bytes < cnt_bytes + al((size_t)n_units * 4)) return MOC_OK;   // too small to count
+    std::vector<int> codes = ordered_units(track_work, order, resident_workgroups());
+    int *d_codes = reinterpret_cast<int *>(buf + cnt_bytes);
+    unsigned long long *d_cnt = reinterpret_cast<unsigned long long *>(buf);
+    HIPCHK(hipMemcpyAsync(d_codes, codes.data(), (size_t)n_units * 4, hipMemcpyHostToDevice, stream));
+    int rc = fill_zero(d_cnt, (size_t)n_units * 16, stream);
+    if (rc) return rc;
+    wa.work = d_codes;
+    wa.exp_pass = 1;
+    wa.exp_count = d_cnt;
+    launch_store(wa, n_units, lds, stream);
+    HIPCHK(hipGetLastError());
+    std::vector<unsigned long long> cnt((size_t)n_units * 2);
+    HIPCHK(hipMemcpyAsync(cnt.data(), d_cnt, cnt.size() * 8, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    // ---- choose: decreasing footprint while the total fits
+    unsigned long long steps_all = 0;
+    std::vector<int> pos(n_units);
+    for (int i = 0; i < n_units; ++i) {
+        pos[i] = i;
+        steps_all += cnt[2 * (size_t)i];
+    }
+    auto foot = [&](int i) { return cnt[2 * (size_t)i] * 64ull * sizeof(Piece) + cnt[2 * (size_t)i + 1] * 4ull; };
+    std::stable_sort(pos.begin(), pos.end(), [&](int x, int y) { return foot(x) > foot(y); });
+    const size_t fixed = al((size_t)n_units * 4) * 2 + al((size_t)n_units * 4) + 4096;
+    {
+        unsigned long long all = 0;
+        for (int i = 0; i < n_units; ++i) all += foot(i);
+        inf.bytes_all = fixed + (size_t)all + 256 * 3;
+    }
+    size_t used = 0;
+    unsigned long long bw_tot = 0, steps_tot = 0;
+    std::vector<char> take(n_units, 0);
+    int ns = 0;
+    for (int i : pos) {
+        const size_t need = (size_t)foot(i);
+        if (fixed + used + need + 256 * 3 > bytes) break;     // the paper stops at the budget
+        if (steps_tot + cnt[2 * (size_t)i] >= (1ull << 32)) break;
+        used += need;
+        bw_tot += cnt[2 * (size_t)i + 1];
+        steps_tot += cnt[2 * (size_t)i];
+        take[i] = 1;
+        ++ns;
+    }
+    inf.wave_steps_total = steps_all;
+    if (ns == 0) {
+        if (out) *out = inf;
+        return MOC_OK;
+    }
+    // stored and remaining units, each in the schedule's order
+    std::vector<int> s_codes, o_codes;
+    std::vector<unsigned> tbase;
+    unsigned long long run = 0;
+    for (int i = 0; i < n_units; ++i) {
+        if (take[i]) {
+            s_codes.push_back(codes[i]);
+            tbase.push_back((unsigned)run);
+            run += cnt[2 * (size_t)i + 1];
+        } else {
+            o_codes.push_back(codes[i]);
+        }
+    }
+    size_t off = 0;
+    const size_t o_scodes = off; off += al(s_codes.size() * 4);
+    const size_t o_ocodes = off; off += al(std::max<size_t>(o_codes.size(), 1) * 4);
+    const size_t o_tbase = off; off += al(tbase.size() * 4);
+    const size_t o_table = off; off += al((bw_tot + 1) * 4);
+    const size_t o_data = off; off += (size_t)steps_tot * 64 * sizeof(Piece);
+    if (off > bytes) {
+        set_error("store layout exceeds the buffer");
+        return MOC_ENOMEM;
+    }
+    HIPCHK(hipMemcpyAsync(buf + o_scodes, s_codes.data(), s_codes.size() * 4, hipMemcpyHostToDevice, stream));
+    if (!o_codes.empty())
+        HIPCHK(hipMemcpyAsync(buf + o_ocodes, o_codes.data(), o_codes.size() * 4, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(buf + o_tbase, tbase.data(), tbase.size() * 4, hipMemcpyHostToDevice, stream));
+    unsigned *d_table = reinterpret_cast<unsigned *>(buf + o_table);
+    // ---- table pass: step count of every bundle window of the stored units
+    wa.work = reinterpret_cast<int *>(buf + o_scodes);
+    wa.exp_tbase = reinterpret_cast<unsigned *>(buf + o_tbase);
+    wa.exp_table = d_table;
+    wa.exp_count = nullptr;
+    wa.exp_pass = 2;
+    launch_store(wa, ns, lds, stream);
+    HIPCHK(hipGetLastError());
+    std::vector<unsigned> table(bw_tot + 1);
+    HIPCHK(hipMemcpyAsync(table.data(), d_table, bw_tot * 4, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    unsigned long long acc = 0;
+    for (unsigned long long i = 0; i < bw_tot; ++i) {
+        const unsigned long long st = table[i];
+        table[i] = (unsigned)acc;
+        acc += st;
+    }
+    table[bw_tot] = (unsigned)acc;
+    if (acc != steps_tot) {
+        set_error("stored-segment step table disagrees with the count pass");
+        return MOC_EDEVICE;
+    }
+    HIPCHK(hipMemcpyAsync(d_table, table.data(), table.size() * 4, hipMemcpyHostToDevice, stream));
+    // ---- record pass
+    wa.exp_pass = 3;
+    wa.exp_data = reinterpret_cast<Piece *>(buf + o_data);
+    launch_store(wa, ns, lds, stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(stream));
+    exp_units = ns;
+    otf_units = (int)o_codes.size();
+    d_exp_work = reinterpret_cast<int *>(buf + o_scodes);
+    d_otf_work = reinterpret_cast<int *>(buf + o_ocodes);
+    d_exp_tbase = reinterpret_cast<unsigned *>(buf + o_tbase);
+    d_exp_table = d_table;
+    d_exp_data = wa.exp_data;
+    inf.units_stored = ns;
+    inf.wave_steps_stored = steps_tot;
+    inf.bytes_used = off;
+    if (out) *out = inf;
+    return MOC_OK;
 }
 
 int window_fit(const Plan &p, bool fp64) {
@@ -1788,15 +2239,16 @@ int Solver::solve_step(const moc_solve_opts &o, double *res) {
         if (!step_ev[b]) HIPCHK(hipEventCreate(&step_ev[b]));
     const FsrArgs f = fsr_args();
     const unsigned fblocks = (unsigned)((f.n + 255) / 256);
-    // the launches of one iteration whose sweep reads psi0 (odd) or psi1 (even)
-    auto issue = [&](bool odd) -> int {
+    // the launches of one iteration whose sweep reads psi0 (odd) or psi1 (even);
+    // launched one by one, the sweep alone sits between the timing events
+    auto issue = [&](bool odd, bool timed) -> int {
         k_source<<<fblocks, 256, 0, stream>>>(f, (int)(kScalBytes / 4));
         SweepArgs a = sweep_args(o.sweep_fp64, o.exp_mode);
         a.psi_in = ws + (odd ? lay.off_psi0 : lay.off_psi1);
         a.psi_out = ws + (odd ? lay.off_psi1 : lay.off_psi0);
-        HIPCHK(hipEventRecord(step_ev[0], stream));
+        if (timed) HIPCHK(hipEventRecord(step_ev[0], stream));
         launch_sweep(a, o.sweep_fp64 != 0);
-        HIPCHK(hipEventRecord(step_ev[1], stream));
+        if (timed) HIPCHK(hipEventRecord(step_ev[1], stream));
         k_finalize<<<fblocks, 256, 0, stream>>>(f);
         k_fold_residual<<<1, 64, 0, stream>>>(f.scal);
         HIPCHK(hipGetLastError());
@@ -1814,7 +2266,7 @@ int Solver::solve_step(const moc_solve_opts &o, double *res) {
                     step_graphs_failed = true;
                     break;
                 }
-                const int rc = issue(b == 1);
+                const int rc = issue(b == 1, false);
                 const hipError_t e = hipStreamEndCapture(stream, &g);
                 if (rc || e != hipSuccess || !g ||
                     hipGraphInstantiate(&step_exec[b], g, nullptr, nullptr, 0) != hipSuccess)
@@ -1827,9 +2279,13 @@ int Solver::solve_step(const moc_solve_opts &o, double *res) {
         }
     }
     if (step_exec[odd ? 1 : 0]) {
+        // a captured iteration is timed as a whole (timing events are not
+        // recorded inside the graph)
+        HIPCHK(hipEventRecord(step_ev[0], stream));
         HIPCHK(hipGraphLaunch(step_exec[odd ? 1 : 0], stream));
+        HIPCHK(hipEventRecord(step_ev[1], stream));
     } else {
-        const int rc = issue(odd);
+        const int rc = issue(odd, true);
         if (rc) return rc;
     }
     HIPCHK(hipStreamSynchronize(stream));

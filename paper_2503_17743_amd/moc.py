@@ -52,6 +52,12 @@ class PlanInfo(C.Structure):
                 ("workspace_bytes_fp64", C.c_size_t), ("line_stride", C.c_int)]
 
 
+class StoreInfo(C.Structure):
+    _fields_ = [("units_stored", C.c_longlong), ("units_total", C.c_longlong),
+                ("wave_steps_stored", C.c_ulonglong), ("wave_steps_total", C.c_ulonglong),
+                ("bytes_used", C.c_size_t), ("bytes_all", C.c_size_t)]
+
+
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iters", C.c_int), ("sweep_fp64", C.c_int),
                 ("exp_mode", C.c_int)]
@@ -97,6 +103,10 @@ def lib():
         "moc_solve_eigen": ([VP, VP, VP, C.POINTER(SolveOpts), C.POINTER(C.c_double), C.POINTER(Stats)], C.c_int),
         "moc_solver_set_walk": ([VP, C.c_int], C.c_int),
         "moc_solver_walk": ([VP, C.POINTER(C.c_int)], C.c_int),
+        "moc_solver_store_segments": ([VP, VP, C.c_size_t, C.POINTER(StoreInfo)], C.c_int),
+        "moc_solver_set_schedule": ([VP, C.c_int, C.c_int], C.c_int),
+        "moc_solver_set_window": ([VP, C.c_int], C.c_int),
+        "moc_solver_window": ([VP, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
         "moc_iterate": ([VP, C.c_int, C.POINTER(SolveOpts), C.POINTER(Stats)], C.c_int),
         "moc_get_flux": ([VP, VP, C.c_size_t], C.c_int),
         "moc_get_volumes": ([VP, VP, C.c_size_t], C.c_int),
@@ -238,6 +248,7 @@ class Solver:
         self._h = h
         self.n_fsr = plan.info["n_fsr"]
         self.G = plan.info["n_groups"]
+        self._store = None
         if walk != "auto":
             self.set_walk(walk)
 
@@ -248,6 +259,7 @@ class Solver:
             self.stream.synchronize()
             lib().moc_solver_destroy(self._h)
             self._h = None
+            self._store = None
 
     def __del__(self):
         try:
@@ -291,6 +303,59 @@ class Solver:
     def set_walk(self, walk="auto"):
         """Transport walk of the FP32 one-chunk sweep: auto, lockstep or lane (per-lane)."""
         _check(lib().moc_solver_set_walk(self._h, self.WALKS[walk]))
+
+    ORDERS = {"longest_first": 0, "natural": 1, "alternating": 2}
+
+    def set_schedule(self, order="longest_first", persistent=False):
+        """Work-unit schedule (section 4.3): longest_first, natural or
+        alternating (decreasing work in groups of the resident workgroup
+        count, every other group reversed); persistent: a grid of resident
+        workgroups sweeping units b, b + grid, ...  Drops any store."""
+        _check(lib().moc_solver_set_schedule(self._h, self.ORDERS[order], int(bool(persistent))))
+        self._store = None
+
+    def store_segments(self, fraction=0.8, max_bytes=None):
+        """Stored-segment sweep (section 4.2): keep the pieces of the units
+        with the largest footprint in a device buffer of at most `fraction`
+        of the free device memory (or max_bytes), replayed by later sweeps.
+        fraction=0 drops the store.  Returns the store info as a dict."""
+        import torch
+        inf = StoreInfo()
+        if fraction <= 0 and not max_bytes:
+            _check(lib().moc_solver_store_segments(self._h, None, 0, C.byref(inf)))
+            self._store = None
+            return {f: getattr(inf, f) for f, _ in StoreInfo._fields_}
+        dev = self.workspace.device
+        # count first with a small buffer, then size the store
+        n_units = 2 * self.info["n_2d_tracks"]
+        small = torch.empty(n_units * 24 + 4096, dtype=torch.uint8, device=dev)
+        self.stream.wait_stream(torch.cuda.current_stream(dev))
+        _check(lib().moc_solver_store_segments(self._h, VP((small.data_ptr() + 255) & ~255),
+                                                small.numel() - 256, C.byref(inf)))
+        self.stream.synchronize()
+        del small
+        torch.cuda.empty_cache()
+        free, _ = torch.cuda.mem_get_info(dev)
+        cap = int(fraction * free) if fraction > 0 else 0
+        if max_bytes:
+            cap = min(cap, int(max_bytes)) if cap else int(max_bytes)
+        nbytes = min(int(inf.bytes_all), cap)
+        self._store = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        self.stream.wait_stream(torch.cuda.current_stream(dev))
+        base = (self._store.data_ptr() + 255) & ~255
+        _check(lib().moc_solver_store_segments(self._h, VP(base), nbytes, C.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in StoreInfo._fields_}
+
+    def set_window(self, threads=0):
+        """Workgroup size of the per-lane sweep: 0 (automatic), 256, 512, 1024."""
+        _check(lib().moc_solver_set_window(self._h, int(threads)))
+        self._store = None
+
+    def window(self):
+        """(workgroup threads, 2D segments per window) of the per-lane sweep."""
+        t, w = C.c_int(), C.c_int()
+        _check(lib().moc_solver_window(self._h, C.byref(t), C.byref(w)))
+        return t.value, w.value
 
     def walk(self):
         w = C.c_int()

@@ -31,9 +31,12 @@ def _progress(log, every, k, n, what):
         log(f"{what}: {k}/{n} requests done")
 
 
-def one_at_a_time(reqs, plans, tol, max_iters, use_arrivals=False, log=None, log_every=0):
+def one_at_a_time(reqs, plans, tol, max_iters, use_arrivals=False, log=None, log_every=0,
+                  stream="own"):
     """FIFO, one request on the GPU at a time: wait for its arrival, bind a
     solver, solve to tol, read the flux back, release the workspace.
+    stream="own": each solve on a stream of its own, every iteration one
+    captured graph; "current": plain launches on torch's current stream.
     `log(msg)` is called every `log_every` completed requests (0: never)."""
     import torch
     arr = _arrivals(reqs, use_arrivals)
@@ -45,7 +48,7 @@ def one_at_a_time(reqs, plans, tol, max_iters, use_arrivals=False, log=None, log
         wait = arr[i] - (time.perf_counter() - t0)
         if wait > 0:
             time.sleep(wait)
-        s = moc.Solver(pl, fp64_boundary=False)
+        s = moc.Solver(pl, fp64_boundary=False, stream=stream)
         s.set_source(r.problem.q)
         phi, st = s.solve(tol=tol, max_iters=max_iters)
         s.close()
@@ -157,8 +160,9 @@ def compare(n_requests, arena_gib, tol=1e-6, max_iters=400, load=0.8, radial=0.0
             axial=0.2, poisson=True, log=None, log_every=0, repeats=2, two_class=True):
     """Continuous batching against one-at-a-time on the same seeded requests:
     first all arriving at once (throughput; with repeats=2 the runs go one,
-    batched, batched, one, so that neither mode always runs on a GPU that has
-    been busy longer), then Poisson arrivals at `load` times the one-at-a-time
+    one plain, batched, batched, one plain, one, so that no mode always runs
+    on a GPU that has been busy longer; the faster one-at-a-time form is the
+    baseline), then Poisson arrivals at `load` times the one-at-a-time
     service rate (latency).  Returns a JSON-ready dict."""
     def say(msg):
         if log is not None:
@@ -171,20 +175,28 @@ def compare(n_requests, arena_gib, tol=1e-6, max_iters=400, load=0.8, radial=0.0
     say(f"serving ({tag}): planned in {time.perf_counter() - t0:.1f} s")
     arena = moc.Server.overhead_bytes(64) + int(arena_gib * (1 << 30))
     kw = dict(log=log, log_every=log_every)
-    order = ("one", "batched", "batched", "one") if repeats >= 2 else ("one", "batched")
-    runs = {"one": [], "batched": []}
+    # one at a time in both launch forms (graph-captured iterations on an own
+    # stream, plain launches); the faster is the baseline of the ratio
+    order = (("one", "one_plain", "batched", "batched", "one_plain", "one") if repeats >= 2
+             else ("one", "one_plain", "batched"))
+    runs = {"one": [], "one_plain": [], "batched": []}
     phi = {}
     for mode in order:
         say(f"serving ({tag}): {mode} ...")
         if mode == "one":
             phi[mode], d = one_at_a_time(reqs, plans, tol, max_iters, **kw)
+        elif mode == "one_plain":
+            phi[mode], d = one_at_a_time(reqs, plans, tol, max_iters, stream="current", **kw)
         else:
             phi[mode], d = run_stream(reqs, plans, tol, max_iters, arena, **kw)
         runs[mode].append(d)
         say(f"serving ({tag}): {mode} {d['wall_s']:.2f} s")
     err = max(max_rel(a, b) for a, b in zip(phi["batched"], phi["one"]))
-    conv = all(st["converged"] for d in runs["batched"] + runs["one"] for st in d["stats"])
-    one, bat = _pool(runs["one"], n_requests), _pool(runs["batched"], n_requests)
+    conv = all(st["converged"] for d in runs["batched"] + runs["one"] + runs["one_plain"]
+               for st in d["stats"])
+    one_g, one_p = _pool(runs["one"], n_requests), _pool(runs["one_plain"], n_requests)
+    bat = _pool(runs["batched"], n_requests)
+    one = one_g if one_g["wall_s"] <= one_p["wall_s"] else one_p
     out = {
         "workload": (f"{n_requests} independent fixed-source lattice solves to residual {tol:g} "
                      f"(4x4/8x8/16x16 cells, 10-50 layers, 1-7 groups, 8-32 azimuthal x 2-6 "
@@ -192,8 +204,13 @@ def compare(n_requests, arena_gib, tol=1e-6, max_iters=400, load=0.8, radial=0.0
         "arena_bytes": arena,
         "all_converged": conv,
         "max_rel_diff_batched_vs_alone": err,
-        "offline": {"order": list(order), "batched": bat, "one_at_a_time": one,
-                    "throughput_ratio": one["wall_s"] / bat["wall_s"]},
+        "offline": {"order": list(order), "batched": bat, "one_at_a_time_graphs": one_g,
+                    "one_at_a_time_plain": one_p,
+                    "baseline": "graphs" if one is one_g else "plain",
+                    "throughput_ratio": one["wall_s"] / bat["wall_s"],
+                    "throughput_ratio_each_run": [o["wall_s"] / b["wall_s"] for o, b in
+                                                  zip(runs["one" if one is one_g else "one_plain"],
+                                                      runs["batched"])]},
     }
     if two_class:
         say(f"serving ({tag}): batched, two classes ...")
@@ -205,7 +222,8 @@ def compare(n_requests, arena_gib, tol=1e-6, max_iters=400, load=0.8, radial=0.0
         rate = load * n_requests / one["wall_s"]
         preqs = P.with_arrivals(probs, rate)
         say(f"serving ({tag}): Poisson arrivals at {rate:.1f}/s, one at a time ...")
-        _, pseq = one_at_a_time(preqs, plans, tol, max_iters, use_arrivals=True, **kw)
+        _, pseq = one_at_a_time(preqs, plans, tol, max_iters, use_arrivals=True,
+                                stream="own" if one is one_g else "current", **kw)
         say(f"serving ({tag}): Poisson one at a time {pseq['wall_s']:.2f} s; batched ...")
         _, pbat = run_stream(preqs, plans, tol, max_iters, arena, use_arrivals=True, **kw)
         say(f"serving ({tag}): Poisson batched {pbat['wall_s']:.2f} s")

@@ -10,6 +10,12 @@
   python -m paper_2503_17743_amd.study eigen [--workload lattice8] [--iters 2000]
       Power iteration on k-eff (synthetic fission data, fissile inclusions)
       to 1e-6: k, iterations and time per iteration.
+  python -m paper_2503_17743_amd.study exp [--workload lattice8] [--iters 10]
+      Stored-segment sweep and work-unit schedules: median sweep time of the
+      on-the-fly sweep under each schedule and of the stored-segment sweep.
+  python -m paper_2503_17743_amd.study window [--workload lattice32] [--iters 5]
+      Median sweep time of the per-lane sweep for each workgroup size
+      (256, 512, 1024 threads) with the largest window its LDS holds.
 
 Progress goes to stderr.
 """
@@ -141,10 +147,87 @@ def eigen(name, tol=1e-6, max_iters=2000, walk="auto"):
     return out
 
 
+SCHEDULES = [
+    # label, (order, persistent), store fraction of free device memory
+    ("otf longest-first (default)", ("longest_first", False), None),
+    ("otf natural order", ("natural", False), None),
+    ("otf natural, persistent grid", ("natural", True), None),
+    ("otf decreasing work, persistent grid", ("longest_first", True), None),
+    ("otf alternating groups, persistent grid", ("alternating", True), None),
+    ("exp longest-first", ("longest_first", False), 0.8),
+    ("exp alternating groups, persistent grid", ("alternating", True), 0.8),
+]
+
+
+def exp_study(name, iters=10, labels=None):
+    """Stored-segment (EXP) sweep and work-unit schedules (paper sections 4.2
+    and 4.3): median sweep time of each variant over `iters` iterations, the
+    store's share of the walk's steps and its setup time."""
+    import torch
+    prob = P.get(name)
+    plan = moc.Plan(prob)
+    out = {"study": "exp", "workload": name, "iterations": iters, "variants": []}
+    for label, sched, store in SCHEDULES:
+        if labels and label not in labels:
+            continue
+        s = moc.Solver(plan, fp64_boundary=False)
+        s.set_source(prob.q)
+        s.set_schedule(*sched)
+        info, t_store = None, 0.0
+        if store:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = s.store_segments(fraction=store)
+            torch.cuda.synchronize()
+            t_store = time.perf_counter() - t0
+        s.reset()
+        s.iterate(2, stats=False)
+        st = s.iterate(iters)
+        row = {"variant": label, "sweep_ms_median": st["sweep_ms_median"],
+               "seg_group_per_s": st["seg_group_updates"] / (st["sweep_ms_median"] * 1e-3)}
+        if info:
+            row.update(store_s=t_store, units_stored=info["units_stored"],
+                       units_total=info["units_total"], store_gb=info["bytes_used"] / 1e9,
+                       steps_stored_frac=info["wave_steps_stored"] / max(info["wave_steps_total"], 1))
+        _log(f"exp {name}: {row}")
+        out["variants"].append(row)
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    return out
+
+
+def window_study(name, iters=5, sizes=(256, 512, 1024)):
+    """Median sweep time of the per-lane sweep for each workgroup size whose
+    window fits (threads, 2D segments per window)."""
+    import torch
+    prob = P.get(name)
+    plan = moc.Plan(prob)
+    out = {"study": "window", "workload": name, "iterations": iters, "sizes": []}
+    s = moc.Solver(plan, fp64_boundary=False)
+    s.set_source(prob.q)
+    out["automatic"] = s.window()
+    for nt in sizes:
+        try:
+            s.set_window(nt)
+        except moc.MocError:
+            continue
+        s.reset()
+        s.iterate(1, stats=False)
+        st = s.iterate(iters)
+        row = {"threads": nt, "segments_per_window": s.window()[1],
+               "sweep_ms_median": st["sweep_ms_median"],
+               "seg_group_per_s": st["seg_group_updates"] / (st["sweep_ms_median"] * 1e-3)}
+        _log(f"window {name}: {row}")
+        out["sizes"].append(row)
+    s.close()
+    return out
+
+
 def main(argv=None):
     import torch
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=("precision", "scale", "eigen"))
+    ap.add_argument("study", choices=("precision", "scale", "eigen", "exp", "window"))
     ap.add_argument("--workload", default=None)
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--walk", choices=("auto", "lockstep", "lane"), default="auto")
@@ -152,6 +235,10 @@ def main(argv=None):
     torch.cuda.set_device(0)
     if args.study == "precision":
         out = precision(args.workload or "lattice32", args.iters or 20)
+    elif args.study == "window":
+        out = window_study(args.workload or "lattice32", args.iters or 5)
+    elif args.study == "exp":
+        out = exp_study(args.workload or "lattice8", args.iters or 10)
     elif args.study == "eigen":
         out = eigen(args.workload or "lattice8", max_iters=args.iters or 2000)
     else:

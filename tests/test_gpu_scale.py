@@ -16,10 +16,11 @@ twice per piece (relative 6e-8 each) and F(tau) to within 4 ulp; over the
 few hundred pieces of a lattice64 line that bounds the outgoing flux at a few
 1e-6 relative, and every flux and source here is positive, so the relative
 error of psi_out is well conditioned.  A tally sums W (psi - qhat) F(tau),
-whose terms change sign, so the tallies are compared through the FSR flux
-that the sample's own tracks estimate by Eq. 4,
-4 pi qhat + 4 pi acc / (Sigma_t sum W l) (path lengths from the oracle), a
-positive quantity held to the 1e-5 flux tolerance.
+whose terms change sign: where psi and qhat nearly cancel the tally is small
+and its relative error meaningless, so each FSR-group tally is compared
+relatively with a floor, the flat-source term qhat Sigma_t sum W l of the
+same sampled path (path lengths from the oracle); the FP32 errors of psi and
+F(tau) bound that comparison by a few 1e-7, and it is held to 1e-5.
 """
 import numpy as np
 import pytest
@@ -60,8 +61,8 @@ def test_sampled_parity_from_the_iterate(moc, name, iters, nthreads):
     assert (opsi > 0).mean() > 0.99
     assert out["max_rel_err_psi_out"] < 2e-6
     assert out["tallies_outside_sample"] == 0
-    # the FSR flux the sampled tracks estimate, held to the flux tolerance
-    assert out["max_rel_err_sample_fsr_flux"] < 1e-5
+    # every tally, relative to itself or to the flat-source floor of its path
+    assert out["max_rel_err_tally"] < 1e-5
 
 
 def _random_input_parity(moc, name, n_items, fp64, seed):
