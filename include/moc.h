@@ -272,6 +272,15 @@ MOC_API int moc_solver_store_segments(moc_solver *s, void *dev_store, size_t sto
  * values. */
 MOC_API int moc_solver_set_schedule(moc_solver *s, int order, int persistent);
 
+/* Within one work unit (section 4.3's load balancing, inside a workgroup):
+ * how the waves of a workgroup share the 64-line bundles of a window.
+ * mode 0 = static (wave w takes bundles w, w + waves, ...); 1 = dynamic (a
+ * wave that finishes a bundle takes the next one not yet taken); -1 =
+ * automatic (dynamic in 1024-thread workgroups, static otherwise; the
+ * default).  Only which wave sweeps which lines changes, so results agree
+ * up to the order of the FP64 tally additions.  EINVAL for other values. */
+MOC_API int moc_solver_set_bundles(moc_solver *s, int mode);
+
 /* Eigenvalue mode: power iteration on k-eff (the multiplication factor the
  * paper's validation reports, Table 2).  nu_sigma_f and chi are [M][G]
  * (M = the plan's materials; finite, >= 0, nu_sigma_f not all zero), copied

@@ -204,6 +204,14 @@ int moc_solver_set_schedule(moc_solver *sv, int order, int persistent) {
     return sv->s.set_schedule(order, persistent);
 }
 
+int moc_solver_set_bundles(moc_solver *sv, int mode) {
+    if (!sv) return fail(MOC_EINVAL, "NULL solver");
+    if (mode < -1 || mode > 1) return fail(MOC_EINVAL, "mode must be -1 (automatic), 0 or 1");
+    sv->s.bundles = mode;
+    sv->s.drop_step_graphs();
+    return MOC_OK;
+}
+
 int moc_solver_set_window(moc_solver *sv, int threads) {
     if (!sv) return fail(MOC_EINVAL, "NULL solver");
     if (threads != 0 && threads != 256 && threads != 512 && threads != 1024)

@@ -53,6 +53,7 @@ struct WinArgs {
     int walk;                 // transport walk of the FP32 one-chunk sweep: 0 lockstep, 1 per-lane
     int small_wg;             // per-lane walk in 256-thread workgroups (Sw sized for them)
     int big_wg;               // per-lane walk in 1024-thread workgroups (Sw sized for them)
+    int dyn_bundles;          // windowed sweep: waves take a window's bundles dynamically
     int persist_units;        // > 0: persistent grid, workgroup b sweeps units b, b + grid, ...
     // stored-segment (EXP) sweep of the per-lane walk
     int exp_pass;             // store pass: 1 count, 2 step table, 3 record

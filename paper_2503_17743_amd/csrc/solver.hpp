@@ -44,6 +44,8 @@ void set_error(const std::string &e);
 const char *last_error();
 int fill_zero(void *p, size_t bytes, hipStream_t st);
 
+double bundles_per_wave(const Plan &p, int Sw, int nt);
+
 struct Solver {
     Layout lay;
     moc_plan_info info{};
@@ -61,6 +63,9 @@ struct Solver {
     int walk = 0;                    // transport walk in use: 0 lockstep, 1 per-lane
     int walk_auto = 0;               // the plan's choice (set at upload)
     int sw256 = 0, sw1024 = 0;       // per-lane walk: windows of 256 / 1024-thread workgroups
+    // per-lane walk: estimated 64-line bundles per wave in a window of the
+    // 256 / 512 / 1024-thread workgroups (weighted by the window's lines)
+    double bpw256 = 0, bpw512 = 0, bpw1024 = 0;
     int window_nt = 0;               // workgroup size the caller chose (0: automatic)
     int lane_nt = 512, lane_win = 0; // the single solver's per-lane sweep: workgroup size, window
     void choose_lane_window();
@@ -92,6 +97,10 @@ struct Solver {
     int order = 0;
     int persistent = 0;
     int set_schedule(int order, int persistent);
+    // bundles of a window: -1 automatic (dynamic in 1024-thread windows),
+    // 0 static (wave w takes w, w + waves, ...), 1 dynamic (an LDS counter)
+    int bundles = -1;
+    bool dyn_bundles() const;
     int upload_work_list();
     // stored-segment (EXP) sweep (paper section 4.2): the recorded pieces of
     // the units with the most pieces, replayed; the other units on the fly

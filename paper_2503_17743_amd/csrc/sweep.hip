@@ -435,7 +435,7 @@ __host__ __device__ inline size_t win_acc_offset(int Sw, int KG, int rbytes) {
 __host__ __device__ inline size_t win_lds_bytes(int Sw, int K, int G, int rbytes) {
     const size_t kg = (size_t)K * G;
     return win_acc_offset(Sw, (int)kg, rbytes) + (size_t)Sw * kg * 8 + ((size_t)Sw + 1) * 8 +
-           (size_t)Sw * G * rbytes + (size_t)Sw * 4 + kWinFixedLds;
+           (size_t)Sw * G * rbytes + (size_t)Sw * 2 * 4 + kWinFixedLds;
 }
 
 
@@ -451,6 +451,11 @@ __device__ inline int div_small(int a, int b) {
 }
 
 __device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Wait until this wave's vector memory operations have completed, among them
+// global_load_lds writes into LDS, which the compiler does not track
+// (s_waitcnt vmcnt(0); the expcnt and lgkmcnt fields left at their maximum)
+__device__ inline void wait_lds_loads() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 __device__ inline float uniform_val(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
@@ -495,15 +500,15 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
     const int KG = K * G;
     const int Sw = wa.Sw;
     // LDS: [reduced source Sw*KG | FP64 tally Sw*KG | segment starts Sw+1 |
-    //       Sigma_t Sw*G | region Sw | line ranges].  The reduced source sits
+    //       Sigma_t Sw*G | regions 2*Sw | line ranges].  The reduced source sits
     // at offset 0, so a lane's per-group loads address it with immediate
     // offsets from one register.
     R *q_l = (R *)smem;
     double *acc_l = (double *)(smem + win_acc_offset(Sw, KG, (int)sizeof(R)));
     double *s_pos = acc_l + (size_t)Sw * KG;
     R *s_st = (R *)(s_pos + Sw + 1);
-    int *s_reg = (int *)(s_st + (size_t)Sw * G);
-    int *r_lo = s_reg + Sw;
+    int *s_reg = (int *)(s_st + (size_t)Sw * G);      // two buffers of Sw
+    int *r_lo = s_reg + 2 * Sw;
     int *r_hi = r_lo + kMaxPolar;
     int *r_st = r_hi + kMaxPolar;       // line stride of each stack's bundles
     int *bpre = r_st + kMaxPolar;
@@ -512,6 +517,7 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
     int *r_full = bpre + kMaxPolar + 1;
     int *r_q = r_full + kMaxPolar;
     int *r_x = r_q + kMaxPolar;
+    int *s_next = r_x + kMaxPolar;      // next bundle of the window to take
     // FP32 stable attenuation: Sigma_t is staged times log2(e), so that
     // Sigma_t l is the exponent of 2 itself
     constexpr bool kL2 = std::is_same<R, float>::value && EXPM == 0 && MODE == 0;
@@ -535,113 +541,235 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
     for (int i = tid; i < Sw * KG; i += NT) acc_l[i] = 0.0;
 
     double s_in = 0.0, s_out = 0.0, leak = 0.0;
-    long long nseg = 0, link_err = 0;
+    // pieces of this lane (a 32-bit count: a lane takes far fewer than 2^31
+    // pieces in one unit), widened for the wave total
+    int nseg = 0;
+    long long link_err = 0;
     // stored-segment sweep: step-table entry of the current window's first
     // bundle (every bundle window of the unit in sweep order), and the count
     // pass's totals of this wave
     unsigned bw_run = (EXP != 0 && wa.exp_tbase) ? wa.exp_tbase[unit] : 0u;
     unsigned long long exp_steps = 0;
 
-    for (int wi = 0; wi < nwin; ++wi) {
+    // Staging of a window: segment starts, regions, Sigma_t and the reduced
+    // source of every FSR-group the window can touch.  Window wi + 1 is
+    // staged during window wi's tally flush, into areas the flush does not
+    // read (the regions, which it reads, are double-buffered).  The reduced
+    // source goes straight from HBM to LDS (global_load_lds: a wave fills 64
+    // consecutive entries, each lane gathering its own), so its loads hold no
+    // registers and their latency overlaps the flush; the few other values
+    // are loaded before the flush and written after it.  The caller waits for
+    // the LDS loads (wait_lds_loads) before the barrier that publishes them.
+    auto window_of = [&](const int wi, int &k0, int &nsw) {
         const int w = dir ? nwin - 1 - wi : wi;
-        const int k0 = f0 + w * Sw;
-        const int nsw = min(k0 + Sw, f1) - k0;
+        k0 = f0 + w * Sw;
+        nsw = min(k0 + Sw, f1) - k0;
+    };
+    // flush of window wi's tally: one HBM atomic per touched FSR-group (the
+    // volume tally has one entry per FSR, kept in the g = 0 slots)
+    auto flush_window = [&](const int wi) {
+        int k0, nsw;
+        window_of(wi, k0, nsw);
+        const int *reg_of = s_reg + (wi & 1) * Sw;
+        for (int i = tid; i < nsw * KG && kPhys; i += NT) {
+            const double v = acc_l[i];
+            if (v != 0.0) {
+                const int kk = i / KG;
+                const int rem = i - kk * KG;
+                const size_t reg = (size_t)reg_of[kk];
+                if (MODE == 0) unsafeAtomicAdd(&a.acc[reg * KG + rem], v);
+                else unsafeAtomicAdd(&a.acc[reg * K + rem / G], v);
+                acc_l[i] = 0.0;
+            }
+        }
+    };
+    const int n_srch = lane;
+    const bool srch = wave == 0 && n_srch < P && (fn < 0 || fn == n_srch);
+    // wave 0: which lines of each polar stack cross window wi (a contiguous
+    // index range, since line extents move monotonically with the line
+    // index), and the bundle prefix over the stacks, into the line-range area
+    // (read by the bundles only, so it is rewritten during the flush)
+    auto search_window = [&](const int wi) {
+        int k0, nsw;
+        window_of(wi, k0, nsw);
         const double wa_ = a.seg_pos[k0];
         const double wb_ = (k0 + nsw < f1) ? a.seg_pos[k0 + nsw] : Lt;
-        // stage the window: segment starts, regions, Sigma_t and the reduced
-        // source of every FSR-group the window can touch
-        for (int i = tid; i < nsw; i += NT) {
-            s_pos[i] = a.seg_pos[k0 + i];
-            s_reg[i] = a.seg_reg[k0 + i];
+        int cs = 0;
+        double c_s = 0.0, ic_s = 0.0, zeta_s = 0.0;
+        long long ilo_s = 0;
+        if (srch) {
+            const long long s = t * P + n_srch;
+            cs = a.cnt[s];
+            c_s = a.cot[az * P + n_srch];
+            ic_s = a.icot[az * P + n_srch];
+            zeta_s = a.zeta[s];
+            ilo_s = a.ilo[s];
         }
-        if (tid == 0) s_pos[nsw] = wb_;
-        if (MODE == 0 && kPhys) {
-            for (int i = tid; i < nsw * G; i += NT) {
-                const int kk = i / G;
-                const int m = a.reg_mat[a.seg_reg[k0 + kk]] * G + (i - kk * G);
-                s_st[i] = kL2 ? (R)(a.sigt64[m] * 1.4426950408889634) : sigt[m];
+        if (tid == 0) *s_next = NT / 64;
+        int lo = 0, hi = -1;
+        if (srch) {
+            const double c = c_s, ic = ic_s;
+            // z of line i at the track start: the value line_base gives
+            auto base_of = [&](int i) { return zeta_s + (double)(ilo_s + i) * a.dz; };
+            auto ls_lt = [&](int i) {
+                double l0, l1;
+                clip_line(base_of(i), c, ic, Lt, a.H, l0, l1);
+                return l0 < wb_;
+            };
+            auto le_gt = [&](int i) {
+                double l0, l1;
+                clip_line(base_of(i), c, ic, Lt, a.H, l0, l1);
+                return l1 > wa_;
+            };
+            int a0 = 0, a1 = cs;        // first true of the rising predicate
+            int b0 = -1, b1 = cs - 1;   // last true of the falling predicate
+            if (c > 0) {
+                while (a0 < a1) { int m = (a0 + a1) >> 1; if (ls_lt(m)) a1 = m; else a0 = m + 1; }
+                while (b0 < b1) { int m = (b0 + b1 + 1) >> 1; if (le_gt(m)) b0 = m; else b1 = m - 1; }
+            } else {
+                while (a0 < a1) { int m = (a0 + a1) >> 1; if (le_gt(m)) a1 = m; else a0 = m + 1; }
+                while (b0 < b1) { int m = (b0 + b1 + 1) >> 1; if (ls_lt(m)) b0 = m; else b1 = m - 1; }
             }
+            lo = a0;
+            hi = b0;
+            if (fn >= 0) {
+                lo = max(lo, (int)fi0);
+                hi = min(hi, (int)fi0 + T - 1);
+            }
+        }
+        // bundles: blocks of S*T consecutive lines, each split into S
+        // bundles of every S-th line.  Lanes S lines (S dz) apart fall in
+        // different layers, so fewer lanes of one instruction add to the
+        // same LDS tally entry.  S = ceil(lines / T), at most the lines
+        // per layer, keeps the bundle count of consecutive bundles.
+        // The per-lane walk packs the lines of all stacks into bundles
+        // instead (the prefix then counts lines): lanes need no common
+        // polar angle there, and the stacks' partial bundles merge.
+        int nb = 0, S = 1, full = 0, q = 0, x = 0;
+        if (hi >= lo) {
+            const int nl = hi - lo + 1;
+            S = min(Smax, (nl + T - 1) / T);
+            const int ST = S * T;
+            const int blocks = (nl + ST - 1) / ST;
+            nb = LANE ? nl : (blocks - 1) * S + min(S, nl - (blocks - 1) * ST);
+            full = (nl - 1) / ST;
+            const int rem = nl - full * ST;
+            q = rem / S;
+            x = rem - q * S;
+        }
+        int sc = nb;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(sc, o, 64);
+            if (lane >= o) sc += v;
+        }
+        r_lo[lane] = lo;
+        r_hi[lane] = hi;
+        r_st[lane] = S;
+        bpre[lane + 1] = sc;
+        if (lane == 0) bpre[0] = 0;
+        if (LANE) {
+            r_full[lane] = full;
+            r_q[lane] = q;
+            r_x[lane] = x;
+        }
+    };
+    // stage window wi; with prev >= 0, flush window prev between the loads
+    // and the writes
+    auto stage_window = [&](const int wi, const int prev) {
+        int k0, nsw;
+        window_of(wi, k0, nsw);
+        // windows of up to 64 segments: lane kk of every wave holds segment
+        // kk's region, read once; waiting for it here keeps every wait out of
+        // the loop of LDS loads below
+        const bool lane_regs = nsw <= 64;
+        int reg_lane = 0;
+        if (lane_regs) {
+            reg_lane = lane < nsw ? a.seg_reg[k0 + lane] : 0;
+            wait_lds_loads();
+        }
+        if (MODE == 0 && kPhys && sizeof(R) == 8) {
+            // FP64 sweep (precision reference): loaded into registers, written
+            // after the flush below
+        } else if (MODE == 0 && kPhys) {
+            // reduced source: chunk c of 64 entries by wave c mod waves, entry
+            // i of segment kk = i / KG.  The window fits the LDS, so nsw * KG
+            // is far below 2^20 (the range of div_small).
+            const int nq = nsw * KG;
+            for (int c = wave; c * 64 < nq; c += NT / 64) {
+                const int i = c * 64 + lane;
+                const int kk = div_small(min(i, nq - 1), KG);
+                int r = __shfl(reg_lane, kk & 63, 64);
+                if (!lane_regs) r = a.seg_reg[k0 + kk];
+                if (i < nq)
+                    __builtin_amdgcn_global_load_lds(
+                        (const __attribute__((address_space(1))) void *)(qhat + (size_t)r * KG + (i - kk * KG)),
+                        (__attribute__((address_space(3))) void *)(q_l + c * 64), 4, 0, 0);
+            }
+        }
+        const double wb = (k0 + nsw < f1) ? a.seg_pos[k0 + nsw] : Lt;
+        double pos = 0.0;
+        int reg = 0;
+        if (tid < nsw) {
+            pos = a.seg_pos[k0 + tid];
+            reg = lane_regs ? reg_lane : a.seg_reg[k0 + tid];
+        }
+        R st = (R)0;
+        if (MODE == 0 && kPhys) {
+            const int kk = tid / G;
+            const int r_st = __shfl(reg_lane, kk & 63, 64);
+            if (tid < nsw * G) {
+                const int m = a.reg_mat[lane_regs ? r_st : a.seg_reg[k0 + kk]] * G + (tid - kk * G);
+                st = kL2 ? (R)(a.sigt64[m] * 1.4426950408889634) : sigt[m];
+            }
+        }
+        if (wave == 0) search_window(wi);
+        if (prev >= 0) flush_window(prev);
+        int *reg_to = s_reg + (wi & 1) * Sw;
+        if (tid < nsw) {
+            s_pos[tid] = pos;
+            reg_to[tid] = reg;
+        }
+        for (int i = tid + NT; i < nsw; i += NT) {
+            s_pos[i] = a.seg_pos[k0 + i];
+            reg_to[i] = a.seg_reg[k0 + i];
+        }
+        if (tid == 0) s_pos[nsw] = wb;
+        if (MODE == 0 && kPhys && sizeof(R) == 8) {
             for (int i = tid; i < nsw * KG; i += NT) {
                 const int kk = i / KG;
                 q_l[i] = qhat[(size_t)a.seg_reg[k0 + kk] * KG + (i - kk * KG)];
             }
         }
-        // wave 0: which lines of each polar stack cross the window (a
-        // contiguous index range, since line extents move monotonically with
-        // the line index), and the bundle prefix over the stacks
-        if (wave == 0) {
-            int lo = 0, hi = -1;
-            const int n = lane;
-            if (n < P && (fn < 0 || fn == n)) {
-                const long long s = t * P + n;
-                const int cs = a.cnt[s];
-                const double c = a.cot[az * P + n], ic = a.icot[az * P + n];
-                auto ls_lt = [&](int i) {
-                    double l0, l1;
-                    clip_line(line_base(a, s, i), c, ic, Lt, a.H, l0, l1);
-                    return l0 < wb_;
-                };
-                auto le_gt = [&](int i) {
-                    double l0, l1;
-                    clip_line(line_base(a, s, i), c, ic, Lt, a.H, l0, l1);
-                    return l1 > wa_;
-                };
-                int a0 = 0, a1 = cs;        // first true of the rising predicate
-                int b0 = -1, b1 = cs - 1;   // last true of the falling predicate
-                if (c > 0) {
-                    while (a0 < a1) { int m = (a0 + a1) >> 1; if (ls_lt(m)) a1 = m; else a0 = m + 1; }
-                    while (b0 < b1) { int m = (b0 + b1 + 1) >> 1; if (le_gt(m)) b0 = m; else b1 = m - 1; }
-                } else {
-                    while (a0 < a1) { int m = (a0 + a1) >> 1; if (le_gt(m)) a1 = m; else a0 = m + 1; }
-                    while (b0 < b1) { int m = (b0 + b1 + 1) >> 1; if (ls_lt(m)) b0 = m; else b1 = m - 1; }
-                }
-                lo = a0;
-                hi = b0;
-                if (fn >= 0) {
-                    lo = max(lo, (int)fi0);
-                    hi = min(hi, (int)fi0 + T - 1);
-                }
-            }
-            // bundles: blocks of S*T consecutive lines, each split into S
-            // bundles of every S-th line.  Lanes S lines (S dz) apart fall in
-            // different layers, so fewer lanes of one instruction add to the
-            // same LDS tally entry.  S = ceil(lines / T), at most the lines
-            // per layer, keeps the bundle count of consecutive bundles.
-            // The per-lane walk packs the lines of all stacks into bundles
-            // instead (the prefix then counts lines): lanes need no common
-            // polar angle there, and the stacks' partial bundles merge.
-            int nb = 0, S = 1, full = 0, q = 0, x = 0;
-            if (hi >= lo) {
-                const int nl = hi - lo + 1;
-                S = min(Smax, (nl + T - 1) / T);
-                const int ST = S * T;
-                const int blocks = (nl + ST - 1) / ST;
-                nb = LANE ? nl : (blocks - 1) * S + min(S, nl - (blocks - 1) * ST);
-                full = (nl - 1) / ST;
-                const int rem = nl - full * ST;
-                q = rem / S;
-                x = rem - q * S;
-            }
-            int sc = nb;
-            for (int o = 1; o < 64; o <<= 1) {
-                const int v = __shfl_up(sc, o, 64);
-                if (lane >= o) sc += v;
-            }
-            r_lo[lane] = lo;
-            r_hi[lane] = hi;
-            r_st[lane] = S;
-            bpre[lane + 1] = sc;
-            if (lane == 0) bpre[0] = 0;
-            if (LANE) {
-                r_full[lane] = full;
-                r_q[lane] = q;
-                r_x[lane] = x;
+        if (MODE == 0 && kPhys) {
+            if (tid < nsw * G) s_st[tid] = st;
+            for (int i = tid + NT; i < nsw * G; i += NT) {
+                const int kk = i / G;
+                const int m = a.reg_mat[a.seg_reg[k0 + kk]] * G + (i - kk * G);
+                s_st[i] = kL2 ? (R)(a.sigt64[m] * 1.4426950408889634) : sigt[m];
             }
         }
-        __syncthreads();
+    };
+    if (nwin > 0) stage_window(0, -1);
+    wait_lds_loads();
+    __syncthreads();
+
+    for (int wi = 0; wi < nwin; ++wi) {
+        int k0, nsw;
+        window_of(wi, k0, nsw);
+        const double wa_ = s_pos[0];
+        const double wb_ = s_pos[nsw];
         const int n_lines = bpre[P];     // per-lane walk: lines of all stacks
         const int total = LANE ? (n_lines + T - 1) / T : bpre[P];
-        for (int bnd = wave; bnd < total; bnd += (NT / 64)) {
+        // bundles: wave w takes w, w + waves, ...; or, with wa.dyn_bundles,
+        // its first one so and then the next untaken one (an LDS counter)
+        // whenever it finishes one, so that the waves end the window together
+        auto next_bundle = [&](int cur) -> int {
+            if (!wa.dyn_bundles) return cur + NT / 64;
+            int v = 0;
+            if (lane == 0) v = atomicAdd(s_next, 1);
+            return uniform(__shfl(v, 0, 64));
+        };
+        for (int bnd = wave; bnd < total; bnd = next_bundle(bnd)) {
             int n = 0, i = 0, nact = 0;
             bool active;
             if constexpr (LANE) {
@@ -995,19 +1123,10 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
         if constexpr (EXP == 1)
             if (wa.exp_pass == 1 && tid == 0) atomicAdd(&wa.exp_count[2 * (size_t)unit + 1], (unsigned long long)total);
         bw_run += (unsigned)total;
-        // flush the window tally: one HBM atomic per touched FSR-group (the
-        // volume tally has one entry per FSR, kept in the g = 0 slots)
-        for (int i = tid; i < nsw * KG && kPhys; i += NT) {
-            const double v = acc_l[i];
-            if (v != 0.0) {
-                const int kk = i / KG;
-                const int rem = i - kk * KG;
-                const size_t reg = (size_t)s_reg[kk];
-                if (MODE == 0) unsafeAtomicAdd(&a.acc[reg * KG + rem], v);
-                else unsafeAtomicAdd(&a.acc[reg * K + rem / G], v);
-                acc_l[i] = 0.0;
-            }
-        }
+        // the window's tally to HBM, and the next window staged meanwhile
+        if (wi + 1 < nwin) stage_window(wi + 1, wi);
+        else flush_window(wi);
+        wait_lds_loads();
         __syncthreads();
     }
     if constexpr (EXP == 1) {
@@ -1017,7 +1136,7 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
     }
     // per-wave totals -> spread scalar slots
     const double v_in = wave_sum(s_in), v_out = wave_sum(s_out), v_lk = wave_sum(leak);
-    const long long ns = wave_sum_ll(MODE == 1 ? (g0 == 0 ? nseg : 0) : nseg * ng);
+    const long long ns = wave_sum_ll(MODE == 1 ? (g0 == 0 ? (long long)nseg : 0) : (long long)nseg * ng);
     const long long le_ = wave_sum_ll(link_err);
     if (lane == 0) {
         const int sl = (int)(((long long)unit * (NT / 64) + wave) % kSlots);
@@ -1676,6 +1795,9 @@ int Solver::upload(const Plan &p) {
         int b = 0;
         while (b < max_seg && win_lds_bytes(b + 1, p.K, p.G, 4) <= kWinLdsBudgetBig) ++b;
         sw1024 = b;
+        bpw256 = bundles_per_wave(p, sw256, 256);
+        bpw512 = bundles_per_wave(p, sw32, kWinThreads);
+        bpw1024 = bundles_per_wave(p, sw1024, kWinThreadsBig);
     }
     choose_lane_window();
     std::vector<std::pair<double, int>> est(p.n2d);
@@ -1798,12 +1920,57 @@ bool Solver::lane_path(const SweepArgs &a, bool fp64) const {
            lane_win >= 1;
 }
 
+// Dynamic bundle assignment pays where a window holds many bundles of
+// unequal length per wave (measured: lattice64, about 16 bundles per wave,
+// 10% faster; lattice32 in 256- and 512-thread windows, 5 to 10 per wave,
+// 1-2% faster); with two or three per wave the static order was as fast or
+// faster (lattice8, lattice32 in 1024-thread windows).
+constexpr double kDynBundlesPerWave = 4.0;
+bool Solver::dyn_bundles() const {
+    if (bundles >= 0) return bundles == 1;
+    const double bpw = lane_nt == 256 ? bpw256 : lane_nt == kWinThreadsBig ? bpw1024 : bpw512;
+    return bpw >= kDynBundlesPerWave;
+}
+
+// Mean number of 64-line bundles per wave in a window of Sw 2D segments swept
+// by nt threads, each window weighted by its line count (a window's time
+// grows with its lines), over up to 256 2D tracks spread through the plan.
+// A line z = base + cot l of a stack crosses the window [wa, wb] when its
+// base lies in an open interval of the two ends; the count of evenly spaced
+// bases in it is rounded, as suits an estimate.
+double bundles_per_wave(const Plan &p, int Sw, int nt) {
+    if (Sw < 1 || p.n2d < 1) return 0.0;
+    const int64_t step = std::max<int64_t>(1, p.n2d / 256);
+    double num = 0.0, den = 0.0;
+    for (int64_t t = 0; t < p.n2d; t += step) {
+        const int64_t f0 = p.seg_first[t], f1 = p.seg_first[t + 1];
+        for (int64_t k0 = f0; k0 < f1; k0 += Sw) {
+            const int64_t k1 = std::min<int64_t>(k0 + Sw, f1);
+            const double wa = p.seg_pos[k0], wb = k1 < f1 ? p.seg_pos[k1] : p.L[t];
+            double lines = 0.0;
+            for (int n = 0; n < p.P; ++n) {
+                const int64_t s = t * p.P + n;
+                const double c = p.cot[p.az[t] * p.P + n];
+                const double lo = c > 0 ? -wb * c : -wa * c, hi = c > 0 ? p.H - wa * c : p.H - wb * c;
+                const double z0 = p.zeta[s] + (double)p.ilo[s] * p.dz;
+                const double i0 = std::max(0.0, std::ceil((lo - z0) / p.dz));
+                const double i1 = std::min((double)p.cnt[s] - 1.0, std::floor((hi - z0) / p.dz));
+                if (i1 >= i0) lines += i1 - i0 + 1.0;
+            }
+            num += lines * lines;
+            den += lines;
+        }
+    }
+    return den > 0.0 ? num / den / 64.0 / (nt / 64) : 0.0;
+}
+
 WinArgs Solver::lane_args(const SweepArgs &a) const {
     WinArgs wa;
     std::memset(&wa, 0, sizeof(wa));
     wa.s = a;
     wa.small_wg = lane_nt == 256 ? 1 : 0;
     wa.big_wg = lane_nt == kWinThreadsBig ? 1 : 0;
+    wa.dyn_bundles = dyn_bundles() ? 1 : 0;
     wa.Sw = lane_win;
     wa.lstride = lstride;
     wa.walk = walk;
@@ -1891,6 +2058,7 @@ void Solver::launch_sweep(SweepArgs a, bool fp64, const int *units, int n_units,
         wa.s = a;
         wa.small_wg = (lane && lane_nt == 256) ? 1 : 0;
         wa.big_wg = (lane && lane_nt == kWinThreadsBig) ? 1 : 0;
+        wa.dyn_bundles = (lane && dyn_bundles()) ? 1 : 0;
         wa.work = units ? units : ws_ptr<int>(ws, lay.off_work);
         wa.filt_n = filt_n;
         wa.filt_i0 = filt_i0;

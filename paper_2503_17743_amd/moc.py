@@ -106,6 +106,7 @@ def lib():
         "moc_solver_store_segments": ([VP, VP, C.c_size_t, C.POINTER(StoreInfo)], C.c_int),
         "moc_solver_set_schedule": ([VP, C.c_int, C.c_int], C.c_int),
         "moc_solver_set_window": ([VP, C.c_int], C.c_int),
+        "moc_solver_set_bundles": ([VP, C.c_int], C.c_int),
         "moc_solver_window": ([VP, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
         "moc_iterate": ([VP, C.c_int, C.POINTER(SolveOpts), C.POINTER(Stats)], C.c_int),
         "moc_get_flux": ([VP, VP, C.c_size_t], C.c_int),
@@ -345,6 +346,13 @@ class Solver:
         base = (self._store.data_ptr() + 255) & ~255
         _check(lib().moc_solver_store_segments(self._h, VP(base), nbytes, C.byref(inf)))
         return {f: getattr(inf, f) for f, _ in StoreInfo._fields_}
+
+    BUNDLES = {"auto": -1, "static": 0, "dynamic": 1}
+
+    def set_bundles(self, mode="auto"):
+        """How a workgroup's waves share a window's bundles: static (wave w
+        takes w, w + waves, ...), dynamic (the next untaken one), or auto."""
+        _check(lib().moc_solver_set_bundles(self._h, self.BUNDLES[mode]))
 
     def set_window(self, threads=0):
         """Workgroup size of the per-lane sweep: 0 (automatic), 256, 512, 1024."""

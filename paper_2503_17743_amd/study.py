@@ -16,6 +16,9 @@
   python -m paper_2503_17743_amd.study window [--workload lattice32] [--iters 5]
       Median sweep time of the per-lane sweep for each workgroup size
       (256, 512, 1024 threads) with the largest window its LDS holds.
+  python -m paper_2503_17743_amd.study bundles [--workload lattice32] [--iters 5]
+      Median sweep time with static and with dynamic assignment of a window's
+      bundles to the waves, for each workgroup size, in interleaved rounds.
 
 Progress goes to stderr.
 """
@@ -224,10 +227,40 @@ def window_study(name, iters=5, sizes=(256, 512, 1024)):
     return out
 
 
+def bundles_study(name, iters=5, sizes=(256, 512, 1024), rounds=2):
+    """Median sweep time with static and with dynamic bundle assignment, for
+    each workgroup size whose window fits, in interleaved rounds."""
+    prob = P.get(name)
+    plan = moc.Plan(prob)
+    out = {"study": "bundles", "workload": name, "iterations": iters, "rows": []}
+    s = moc.Solver(plan, fp64_boundary=False)
+    s.set_source(prob.q)
+    out["automatic"] = s.window()
+    for nt in sizes:
+        try:
+            s.set_window(nt)
+        except moc.MocError:
+            continue
+        for r in range(rounds):
+            for mode in ("static", "dynamic"):
+                s.set_bundles(mode)
+                s.reset()
+                s.iterate(1, stats=False)
+                st = s.iterate(iters)
+                row = {"threads": nt, "segments_per_window": s.window()[1], "bundles": mode,
+                       "round": r, "sweep_ms_median": st["sweep_ms_median"],
+                       "seg_group_per_s": st["seg_group_updates"] / (st["sweep_ms_median"] * 1e-3)}
+                _log(f"bundles {name}: {row}")
+                out["rows"].append(row)
+    s.set_bundles("auto")
+    s.close()
+    return out
+
+
 def main(argv=None):
     import torch
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=("precision", "scale", "eigen", "exp", "window"))
+    ap.add_argument("study", choices=("precision", "scale", "eigen", "exp", "window", "bundles"))
     ap.add_argument("--workload", default=None)
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--walk", choices=("auto", "lockstep", "lane"), default="auto")
@@ -237,6 +270,8 @@ def main(argv=None):
         out = precision(args.workload or "lattice32", args.iters or 20)
     elif args.study == "window":
         out = window_study(args.workload or "lattice32", args.iters or 5)
+    elif args.study == "bundles":
+        out = bundles_study(args.workload or "lattice32", args.iters or 5)
     elif args.study == "exp":
         out = exp_study(args.workload or "lattice8", args.iters or 10)
     elif args.study == "eigen":
