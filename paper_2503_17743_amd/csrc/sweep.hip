@@ -821,28 +821,20 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
             const double base = line_base(a, s, i);
             double ls = 1e300, le = -1e300;
             if (active) clip_line(base, c, ic, Lt, a.H, ls, le);
-            // segments of the window touched by the bundle
-            double u_lo, u_hi;
-            if constexpr (LANE) {
-                // lines of several stacks: the extremes over the wave
-                double mn = ls, mx = le;
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) {
-                    mn = fmin(mn, __shfl_xor(mn, o, 64));
-                    mx = fmax(mx, __shfl_xor(mx, o, 64));
-                }
-                u_lo = fmax(mn, wa_);
-                u_hi = fmin(mx, wb_);
-            } else {
+            // segments of the window the bundle can touch, [ka, kb]: with the
+            // per-lane walk the whole window (each lane finds its own first
+            // segment and stops where its line ends, so a narrower range
+            // would change no piece and only cost two wave reductions and
+            // two bisections per bundle); with the lockstep walk the range
+            // the bundle's lines span, which the wave walks together
+            int ka = 0, kb = nsw - 1;
+            if constexpr (!LANE) {
                 // the extents of consecutive lines of one stack move
                 // monotonically with the line index, so the first and last
                 // line bound them
                 const int last = (nact - 1) * C;
-                u_lo = fmax(fmin(__shfl(ls, 0, 64), __shfl(ls, last, 64)), wa_);
-                u_hi = fmin(fmax(__shfl(le, 0, 64), __shfl(le, last, 64)), wb_);
-            }
-            int ka = 0, kb = nsw - 1;
-            {
+                const double u_lo = fmax(fmin(__shfl(ls, 0, 64), __shfl(ls, last, 64)), wa_);
+                const double u_hi = fmin(fmax(__shfl(le, 0, 64), __shfl(le, last, 64)), wb_);
                 int lo2 = 0, hi2 = nsw;
                 while (hi2 - lo2 > 1) { const int m = (lo2 + hi2) >> 1; if (s_pos[m] <= u_lo) lo2 = m; else hi2 = m; }
                 ka = lo2;
@@ -850,10 +842,10 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                 hi2 = nsw;
                 while (hi2 - lo2 > 1) { const int m = (lo2 + hi2) >> 1; if (s_pos[m] < u_hi) lo2 = m; else hi2 = m; }
                 kb = lo2;
+                // the same for every lane (the bounds came through lane shuffles)
+                ka = uniform(ka);
+                kb = uniform(kb);
             }
-            // the same for every lane (the bounds came through lane shuffles)
-            ka = uniform(ka);
-            kb = uniform(kb);
             const bool starts = dir == 0 ? (ls >= wa_) : (le <= wb_);
             const bool ends = dir == 0 ? (le <= wb_) : (ls >= wa_);
             const long long slot = 2 * (a.trk_off[s] + i) + dir;
@@ -947,8 +939,7 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                 }
             } else if constexpr (LANE) {
                 // the lane's first 2D segment: the one holding its start in
-                // sweep order (inside [ka, kb], since its extent is inside the
-                // bundle's)
+                // sweep order (inside the window, since its extent is)
                 const int kstep = dir ? -1 : 1;
                 int sg = dir ? kb : ka;
                 double e = 0.0;
