@@ -68,27 +68,30 @@ __host__ __device__ inline size_t slot_index(int q, int slot) {
 // ------------------------------------------------------------------ helpers
 
 constexpr float kLog2e = 1.44269504088896341f;
-// 1 - e^{-tau} switches form at u = tau log2(e) = 1/2 (tau = ln(2)/2)
-constexpr float kSmallU = 0.5f;
-
-// F = 1 - 2^{-u} for u >= 0 without cancellation (the attenuation factor
-// 1 - e^{-tau} of Eq. 3 at u = tau log2(e)).  Below u = 1/2, F = u p(u), with
-// p the degree-4 interpolant of (1 - 2^-u)/u at the Chebyshev nodes of
-// [0, 1/2]; above it the hardware exp2 is used, where F >= 0.29 limits the
-// cancellation to about 2 ulp.  Measured against FP64 over tau in [2^-30, 40]
-// with u = tau log2(e) rounded to FP32: within 2 ulp.
-__device__ inline float one_minus_exp2_f32(float u) {
-    float p = 1.15544000e-3f;
-    p = fmaf(p, u, -9.54227522e-3f);
-    p = fmaf(p, u, 5.54907210e-2f);
-    p = fmaf(p, u, -2.40225673e-1f);
-    p = fmaf(p, u, 6.93147182e-1f);
-    const float large = 1.0f - __builtin_amdgcn_exp2f(-u);
-    return u < kSmallU ? u * p : large;
+// F = 1 - 2^{-u} at u = s l (the attenuation factor 1 - e^{-tau} of Eq. 3,
+// with s = Sigma_t log2(e) and l the piece length), without cancellation,
+// from one hardware exp2 and one hardware log2.  With e = 2^{-u'}(1 + d) the
+// value the exp2 returns for u' = s l rounded, 1 - e is exact for e >= 1/2
+// but off by e d, which for small u is most of F.  log2 e = -u' + d/ln 2 up
+// to the log2's own error, about one ulp of its result (also for e near 1,
+// where that result is small), so du = s l + log2 e (one rounding) =
+// (s l - u') + d/ln 2, and F = (1 - e) + ln 2 e du = 1 - 2^{-s l} + O(d^2):
+// the correction also takes back the rounding of s l.  The product e du is
+// a legacy multiply (0 x anything = 0), so that where e underflows to 0 and
+// log2 e is -inf, F comes out as 1.  Measured on the device over every float
+// u in [2^-30, 256] (s = 1): within 1.71 ulp of FP64.  Split in two so that
+// a caller evaluating several groups can issue all its exp2 first.
+__device__ inline float atten_e(float s, float l) { return __builtin_amdgcn_exp2f(-(s * l)); }
+__device__ inline float atten_from_e(float s, float l, float e) {
+    const float du = fmaf(s, l, __builtin_amdgcn_logf(e));
+    float m;
+    asm("v_mul_legacy_f32 %0, %1, %2" : "=v"(m) : "v"(e), "v"(du));
+    return fmaf(0.693147182f, m, 1.0f - e);
 }
+__device__ inline float atten_f32(float s, float l) { return atten_from_e(s, l, atten_e(s, l)); }
 
-// F(tau) = 1 - e^{-tau} for tau >= 0 (the same evaluation, from tau itself)
-__device__ inline float one_minus_exp_f32(float t) { return one_minus_exp2_f32(t * kLog2e); }
+// F(tau) = 1 - e^{-tau} for tau >= 0 (the same evaluation, s = log2(e))
+__device__ inline float one_minus_exp_f32(float t) { return atten_f32(kLog2e, t); }
 
 template <typename R>
 __device__ inline R one_minus_exp(R tau, int exp_mode);
@@ -892,6 +895,36 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
             };
+            // Eq. 3 on one piece for the lane's groups (one-chunk lanes, C1):
+            // d = W (psi - qhat) F(Sigma_t l); with the FP32 exp2 form, all
+            // groups' exp2 are issued first, so that no transcendental waits on
+            // the one just issued (the per-lane walk and its replay share this,
+            // so both give the same fluxes bit for bit)
+            auto transport = [&](const R (&qv)[kGL], const R (&stv)[kGL], const R lr) {
+                if constexpr (kL2) {
+                    float e[kGL];
+#pragma unroll
+                    for (int j = 0; j < kGL; ++j)
+                        if (j < GL) e[j] = atten_e((float)stv[j], (float)lr);
+#pragma unroll
+                    for (int j = 0; j < kGL; ++j)
+                        if (j < GL) {
+                            const R f = (R)atten_from_e((float)stv[j], (float)lr, e[j]);
+                            const R d = fma(-Wr, qv[j], psi[j]) * f;
+                            psi[j] -= d;
+                            pend[j] = d;
+                        }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < kGL; ++j)
+                        if (j < GL) {
+                            const R f = one_minus_exp<R>(stv[j] * lr, EXPM);
+                            const R d = fma(-Wr, qv[j], psi[j]) * f;
+                            psi[j] -= d;
+                            pend[j] = d;
+                        }
+                }
+            };
             if constexpr (LANE && EXP == 2) {
                 // replay of the recorded pieces of this bundle window: the
                 // same transport arithmetic as the per-lane walk below, with
@@ -924,15 +957,7 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                                 stv[j] = s_st[lst + j];
                             }
                         flush_pending();
-#pragma unroll
-                        for (int j = 0; j < kGL; ++j)
-                            if (j < GL) {
-                                const R f = kL2 ? (R)one_minus_exp2_f32((float)(stv[j] * lr))
-                                                : one_minus_exp<R>(stv[j] * lr, EXPM);
-                                const R d = fma(-Wr, qv[j], psi[j]) * f;
-                                psi[j] -= d;
-                                pend[j] = d;
-                            }
+                        transport(qv, stv, lr);
                         pend_li = li;
                         nseg += cur.len > 0.0f;
                     }
@@ -990,15 +1015,7 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                                 stv[j] = s_st[lst + j];
                             }
                         flush_pending();
-#pragma unroll
-                        for (int j = 0; j < kGL; ++j)
-                            if (j < GL) {
-                                const R f = kL2 ? (R)one_minus_exp2_f32((float)(stv[j] * lr))
-                                                : one_minus_exp<R>(stv[j] * lr, EXPM);
-                                const R d = fma(-Wr, qv[j], psi[j]) * f;
-                                psi[j] -= d;
-                                pend[j] = d;
-                            }
+                        transport(qv, stv, lr);
                         pend_li = li;
                         }
                         nseg += valid;
@@ -1062,7 +1079,7 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                     for (int j = 0; j < kGL; ++j)
                         if (j < GL) {
                             // d = W (psi - qhat) (1 - e^-tau)  (Eq. 3 on the scaled flux)
-                            const R f = kL2 ? (R)one_minus_exp2_f32((float)(stv[j] * lr))
+                            const R f = kL2 ? (R)atten_f32((float)stv[j], (float)lr)
                                             : one_minus_exp<R>(stv[j] * lr, EXPM);
                             R d = fma(-Wr, qv[j], psi[j]) * f;
                             if (!C1 && j >= ng) d = (R)0;
