@@ -21,8 +21,8 @@ def moc():
 def _taus():
     rng = np.random.default_rng(7)
     dense = np.logspace(-30 * np.log10(2), np.log10(40.0), 400_000)
-    # around the switch between the two evaluation branches (u = tau log2(e)
-    # = 1/2) and the ends
+    # around u = tau log2(e) = 1/2 (where an earlier form switched between a
+    # polynomial and exp2) and the ends
     sw = 0.5 * np.log(2.0)
     edges = np.concatenate([np.linspace(sw - 0.05, sw + 0.05, 20_001), np.linspace(0.45, 0.55, 20_001),
                             [2.0 ** -30, 40.0, 0.5, sw]])
