@@ -16,6 +16,7 @@ struct SweepArgs {
     const long long *trk_off, *chunk_off;         // [n_stacks+1]
     const void *sigt;                             // [M][G] float or double
     const double *sigt64;                         // [M][G] double (always)
+    const float *seg_st;                          // [nseg][G] Sigma_t log2(e) of each 2D segment (FP32)
     const void *qhat;                             // [n_fsr][G] float or double
     double *acc;                                  // [n_fsr][G]
     void *psi_in;                                 // boundary buffer read this sweep

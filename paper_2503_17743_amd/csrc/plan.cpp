@@ -522,6 +522,7 @@ Layout make_layout(const Plan &p, bool psi64) {
     size_t nseg = p.seg_pos.size();
     l.off_seg_pos = take((nseg + 1) * 8);
     l.off_seg_reg = take((nseg + 1) * 4);
+    l.off_seg_st = take((nseg + 1) * (size_t)p.G * 4);
     l.off_reg_mat = take(p.n_regions * 4);
     l.off_zeta = take(p.n_stacks * 8);
     l.off_ilo = take(p.n_stacks * 8);

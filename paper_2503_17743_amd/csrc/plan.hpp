@@ -76,6 +76,7 @@ struct Layout {
     size_t off_cot = 0, off_secl = 0, off_icot = 0, off_wgt = 0;  // [A2][P] doubles
     size_t off_t_len = 0, off_t_first = 0, off_t_meta = 0, off_t_link = 0;
     size_t off_seg_pos = 0, off_seg_reg = 0, off_reg_mat = 0;
+    size_t off_seg_st = 0;          // [nseg][G] float: Sigma_t log2(e) per 2D segment
     size_t off_zeta = 0, off_ilo = 0, off_cnt = 0, off_trk_off = 0, off_chunk_off = 0;
     size_t off_sigt32 = 0, off_sigt64 = 0, off_sigs = 0;
     size_t off_q = 0, off_qhat32 = 0, off_qhat64 = 0, off_acc = 0, off_phi = 0, off_vol = 0;

@@ -676,65 +676,99 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
             r_x[lane] = x;
         }
     };
+    // n dwords from HBM straight into LDS (global_load_lds: chunk c of 64
+    // dwords by wave c mod waves, each lane copying one; the reduced source
+    // below moves 16 B per lane, the LDS taking lane L's at 16 L); the caller waits
+    // for them (wait_lds_loads) before the barrier that publishes them
+    auto copy_to_lds = [&](void *dst, const void *src, const int n) {
+        for (int c = wave; c * 64 < n; c += NT / 64) {
+            const int i = c * 64 + lane;
+            if (i < n)
+                __builtin_amdgcn_global_load_lds(
+                    (const __attribute__((address_space(1))) void *)((const unsigned *)src + i),
+                    (__attribute__((address_space(3))) void *)((unsigned *)dst + c * 64), 4, 0, 0);
+        }
+    };
     // stage window wi; with prev >= 0, flush window prev between the loads
     // and the writes
     auto stage_window = [&](const int wi, const int prev) {
         int k0, nsw;
         window_of(wi, k0, nsw);
-        // windows of up to 64 segments: lane kk of every wave holds segment
-        // kk's region, read once; waiting for it here keeps every wait out of
-        // the loop of LDS loads below
-        const bool lane_regs = nsw <= 64;
-        int reg_lane = 0;
-        if (lane_regs) {
-            reg_lane = lane < nsw ? a.seg_reg[k0 + lane] : 0;
-            wait_lds_loads();
-        }
-        if (MODE == 0 && kPhys && sizeof(R) == 8) {
-            // FP64 sweep (precision reference): loaded into registers, written
-            // after the flush below
-        } else if (MODE == 0 && kPhys) {
-            // reduced source: chunk c of 64 entries by wave c mod waves, entry
-            // i of segment kk = i / KG.  The window fits the LDS, so nsw * KG
-            // is far below 2^20 (the range of div_small).
-            const int nq = nsw * KG;
-            for (int c = wave; c * 64 < nq; c += NT / 64) {
-                const int i = c * 64 + lane;
-                const int kk = div_small(min(i, nq - 1), KG);
-                int r = __shfl(reg_lane, kk & 63, 64);
-                if (!lane_regs) r = a.seg_reg[k0 + kk];
-                if (i < nq)
-                    __builtin_amdgcn_global_load_lds(
-                        (const __attribute__((address_space(1))) void *)(qhat + (size_t)r * KG + (i - kk * KG)),
-                        (__attribute__((address_space(3))) void *)(q_l + c * 64), 4, 0, 0);
+        // FP32 sweep: segment starts, regions and Sigma_t rows are copies of
+        // contiguous HBM ranges, and the reduced source a gather by region,
+        // all loaded straight into LDS; the FP64 sweep and the naive-exp
+        // study load into registers and write after the flush
+        constexpr bool kDirect = sizeof(R) == 4;
+        int *reg_to = s_reg + (wi & 1) * Sw;
+        if constexpr (kDirect) {
+            copy_to_lds(s_pos, a.seg_pos + k0, 2 * nsw);
+            copy_to_lds(reg_to, a.seg_reg + k0, nsw);
+            if (MODE == 0 && kPhys) {
+                if (kL2) copy_to_lds(s_st, a.seg_st + (size_t)k0 * G, nsw * G);
+                // reduced source: entry i of segment kk = i / KG, from the
+                // region lane kk of every wave holds for windows of up to 64
+                // segments (waiting for it here keeps every wait out of the
+                // loop), else read per entry.  The window fits the LDS, so
+                // nsw * KG is far below 2^20 (the range of div_small).
+                const int nq = nsw * KG;
+                const bool lane_regs = nsw <= 64;
+                int reg_lane = 0;
+                if (lane_regs) {
+                    reg_lane = lane < nsw ? a.seg_reg[k0 + lane] : 0;
+                    wait_lds_loads();
+                }
+                if (KG % 4 == 0) {
+                    // 16 B per lane (four entries of one row: rows and the
+                    // workspace are 16-byte aligned), a quarter of the loads
+                    for (int c = wave; c * 256 < nq; c += NT / 64) {
+                        const int i = c * 256 + 4 * lane;
+                        const int kk = div_small(min(i, nq - 4), KG);
+                        int r = __shfl(reg_lane, kk & 63, 64);
+                        if (!lane_regs) r = a.seg_reg[k0 + kk];
+                        if (i < nq)
+                            __builtin_amdgcn_global_load_lds(
+                                (const __attribute__((address_space(1))) void *)(qhat + (size_t)r * KG + (i - kk * KG)),
+                                (__attribute__((address_space(3))) void *)(q_l + c * 256), 16, 0, 0);
+                    }
+                } else {
+                    for (int c = wave; c * 64 < nq; c += NT / 64) {
+                        const int i = c * 64 + lane;
+                        const int kk = div_small(min(i, nq - 1), KG);
+                        int r = __shfl(reg_lane, kk & 63, 64);
+                        if (!lane_regs) r = a.seg_reg[k0 + kk];
+                        if (i < nq)
+                            __builtin_amdgcn_global_load_lds(
+                                (const __attribute__((address_space(1))) void *)(qhat + (size_t)r * KG + (i - kk * KG)),
+                                (__attribute__((address_space(3))) void *)(q_l + c * 64), 4, 0, 0);
+                    }
+                }
             }
         }
         const double wb = (k0 + nsw < f1) ? a.seg_pos[k0 + nsw] : Lt;
         double pos = 0.0;
         int reg = 0;
-        if (tid < nsw) {
+        if (!kDirect && tid < nsw) {
             pos = a.seg_pos[k0 + tid];
-            reg = lane_regs ? reg_lane : a.seg_reg[k0 + tid];
+            reg = a.seg_reg[k0 + tid];
         }
+        constexpr bool kStRegs = !(kDirect && kL2);
         R st = (R)0;
-        if (MODE == 0 && kPhys) {
+        if (MODE == 0 && kPhys && kStRegs && tid < nsw * G) {
             const int kk = tid / G;
-            const int r_st = __shfl(reg_lane, kk & 63, 64);
-            if (tid < nsw * G) {
-                const int m = a.reg_mat[lane_regs ? r_st : a.seg_reg[k0 + kk]] * G + (tid - kk * G);
-                st = kL2 ? (R)(a.sigt64[m] * 1.4426950408889634) : sigt[m];
-            }
+            const int m = a.reg_mat[a.seg_reg[k0 + kk]] * G + (tid - kk * G);
+            st = kL2 ? (R)(a.sigt64[m] * 1.4426950408889634) : sigt[m];
         }
         if (wave == 0) search_window(wi);
         if (prev >= 0) flush_window(prev);
-        int *reg_to = s_reg + (wi & 1) * Sw;
-        if (tid < nsw) {
-            s_pos[tid] = pos;
-            reg_to[tid] = reg;
-        }
-        for (int i = tid + NT; i < nsw; i += NT) {
-            s_pos[i] = a.seg_pos[k0 + i];
-            reg_to[i] = a.seg_reg[k0 + i];
+        if constexpr (!kDirect) {
+            if (tid < nsw) {
+                s_pos[tid] = pos;
+                reg_to[tid] = reg;
+            }
+            for (int i = tid + NT; i < nsw; i += NT) {
+                s_pos[i] = a.seg_pos[k0 + i];
+                reg_to[i] = a.seg_reg[k0 + i];
+            }
         }
         if (tid == 0) s_pos[nsw] = wb;
         if (MODE == 0 && kPhys && sizeof(R) == 8) {
@@ -743,7 +777,7 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                 q_l[i] = qhat[(size_t)a.seg_reg[k0 + kk] * KG + (i - kk * KG)];
             }
         }
-        if (MODE == 0 && kPhys) {
+        if (MODE == 0 && kPhys && kStRegs) {
             if (tid < nsw * G) s_st[tid] = st;
             for (int i = tid + NT; i < nsw * G; i += NT) {
                 const int kk = i / G;
@@ -1703,6 +1737,7 @@ SweepArgs Solver::sweep_args(int fp64, int exp_mode) const {
     a.sigt = fp64 ? (const void *)ws_ptr<double>(ws, lay.off_sigt64)
                   : (const void *)ws_ptr<float>(ws, lay.off_sigt32);
     a.sigt64 = ws_ptr<double>(ws, lay.off_sigt64);
+    a.seg_st = ws_ptr<float>(ws, lay.off_seg_st);
     a.qhat = fp64 ? (const void *)ws_ptr<double>(ws, lay.off_qhat64)
                   : (const void *)ws_ptr<float>(ws, lay.off_qhat32);
     a.acc = ws_ptr<double>(ws, lay.off_acc);
@@ -1781,6 +1816,17 @@ int Solver::upload(const Plan &p) {
     HIPCHK(put(lay.off_sigt32, sigt32.data(), sigt32.size() * 4));
     HIPCHK(put(lay.off_sigt64, p.sigt.data(), p.sigt.size() * 8));
     HIPCHK(put(lay.off_sigs, p.sigs.data(), p.sigs.size() * 8));
+    {
+        // Sigma_t log2(e) of every 2D segment's material, rounded once to FP32
+        // (the FP32 sweep copies a window's rows straight into LDS)
+        std::vector<float> seg_st(p.seg_reg.size() * (size_t)p.G);
+        for (size_t k = 0; k < p.seg_reg.size(); ++k) {
+            const int m = p.reg_mat[p.seg_reg[k]];
+            for (int g = 0; g < p.G; ++g)
+                seg_st[k * p.G + g] = (float)(p.sigt[(size_t)m * p.G + g] * 1.4426950408889634);
+        }
+        HIPCHK(put(lay.off_seg_st, seg_st.data(), seg_st.size() * 4));
+    }
     // windowed sweep: window size from the LDS budget, and the work list of
     // (2D track, direction) units ordered by decreasing work (lines x 2D
     // segments), so the longest units start first
