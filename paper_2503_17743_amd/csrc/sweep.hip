@@ -624,14 +624,29 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                 clip_line(base_of(i), c, ic, Lt, a.H, l0, l1);
                 return l1 > wa_;
             };
-            int a0 = 0, a1 = cs;        // first true of the rising predicate
-            int b0 = -1, b1 = cs - 1;   // last true of the falling predicate
-            if (c > 0) {
-                while (a0 < a1) { int m = (a0 + a1) >> 1; if (ls_lt(m)) a1 = m; else a0 = m + 1; }
-                while (b0 < b1) { int m = (b0 + b1 + 1) >> 1; if (le_gt(m)) b0 = m; else b1 = m - 1; }
-            } else {
-                while (a0 < a1) { int m = (a0 + a1) >> 1; if (le_gt(m)) a1 = m; else a0 = m + 1; }
-                while (b0 < b1) { int m = (b0 + b1 + 1) >> 1; if (ls_lt(m)) b0 = m; else b1 = m - 1; }
+            // The line bases are evenly spaced, so the two ends have closed
+            // forms (for c > 0 a line starts before wb when base > -wb c and
+            // ends after wa when base < H - wa c; for c < 0 the same with wa
+            // and wb exchanged).  Each estimate is accepted only when the
+            // exact predicate confirms it at the estimate and its neighbour,
+            // else found by bisection, so the result is the bisection's.
+            auto rising = [&](int i) { return c > 0 ? ls_lt(i) : le_gt(i); };    // false ... true
+            auto falling = [&](int i) { return c > 0 ? le_gt(i) : ls_lt(i); };   // true ... false
+            const double z0 = zeta_s + (double)ilo_s * a.dz;
+            const double z_lo = c > 0 ? -wb_ * c : -wa_ * c, z_hi = c > 0 ? a.H - wa_ * c : a.H - wb_ * c;
+            int a0 = (int)fmin(fmax(floor((z_lo - z0) * a.inv_dz) + 1.0, 0.0), (double)cs);
+            int b0 = (int)fmin(fmax(ceil((z_hi - z0) * a.inv_dz) - 1.0, -1.0), (double)cs - 1.0);
+            // first true of the rising predicate in [0, cs] (cs: none)
+            if (!((a0 == cs || rising(a0)) && (a0 == 0 || !rising(a0 - 1)))) {
+                int a1 = cs;
+                a0 = 0;
+                while (a0 < a1) { int m = (a0 + a1) >> 1; if (rising(m)) a1 = m; else a0 = m + 1; }
+            }
+            // last true of the falling predicate in [-1, cs - 1] (-1: none)
+            if (!((b0 == -1 || falling(b0)) && (b0 == cs - 1 || !falling(b0 + 1)))) {
+                int b1 = cs - 1;
+                b0 = -1;
+                while (b0 < b1) { int m = (b0 + b1 + 1) >> 1; if (falling(m)) b0 = m; else b1 = m - 1; }
             }
             lo = a0;
             hi = b0;
