@@ -31,7 +31,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_SEG_GROUP = 12.0      # 4 B reduced-source gather + 8 B FP64 tally update
 # Vector ALU issue peak: 256 CUs x 4 SIMDs, each retiring one wave64 VALU
-# instruction every 4 cycles (16 lanes per cycle), at 2.4 GHz
+# issue slot every 4 cycles (16 lanes per cycle), at 2.4 GHz; an ordinary
+# instruction takes one slot, a transcendental two
 VALU_PEAK_INSTR_PER_S = 256 * 4 * 2.4e9 / 4
 
 
@@ -265,17 +266,21 @@ def small_workload(name, steps, oracle_iters, cpu_leg):
 
 
 def roofline(segg, sweep_s, counters):
-    """The sweep's binding roof: vector ALU issue (measured wave64 VALU
-    instructions per launch over the kernel time), with the algorithmic HBM
-    figure and the measured DRAM traffic as context."""
+    """The sweep's binding roof: vector ALU issue (measured wave64 VALU issue
+    slots per launch, SQ_ACTIVE_INST_VALU, in which a transcendental counts
+    twice, over the kernel time), with the instruction count, the algorithmic
+    HBM figure and the measured DRAM traffic as context."""
     eff_gbs = BYTES_PER_SEG_GROUP * segg / sweep_s / 1e9
     line = {"bound": "alu", "achieved": None, "peak": VALU_PEAK_INSTR_PER_S,
-            "unit": "wave64 VALU instr/s", "frac": None, "traffic": None,
+            "unit": "wave64 VALU issue slots/s", "frac": None, "traffic": None,
             "effective_hbm_gbs": eff_gbs, "effective_hbm_frac": eff_gbs / HBM_PEAK_GBS}
     if counters is not None:
         valu = counters["valu_instructions_per_launch"]
-        line["achieved"] = valu / sweep_s
+        slots = counters.get("valu_issue_slots_per_launch", valu)
+        line["achieved"] = slots / sweep_s
         line["frac"] = line["achieved"] / VALU_PEAK_INSTR_PER_S
+        line["valu_instructions_per_s"] = valu / sweep_s
+        line["valu_instructions_frac"] = valu / sweep_s / VALU_PEAK_INSTR_PER_S
         line["traffic"] = counters.get("hbm_bytes_per_launch")
         if line["traffic"]:
             line["dram_gbs"] = line["traffic"] / sweep_s / 1e9
