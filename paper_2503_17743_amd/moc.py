@@ -84,6 +84,11 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    # torch carries its own HIP runtime under the same soname as the one the
+    # library links against.  Loading torch first makes the dynamic loader bind
+    # the library to that copy, so the process holds one HIP runtime and the
+    # workspace pointers and streams torch hands over are valid in the library.
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     sig = {
         "moc_last_error": ([], C.c_char_p),

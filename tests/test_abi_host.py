@@ -32,6 +32,25 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
 
 
+def test_library_shares_torchs_hip_runtime():
+    """Loading the library before anything imported torch must still leave one
+    HIP runtime in the process, torch's (two copies cannot share device
+    pointers or streams)."""
+    import subprocess
+    import sys
+    code = ("from paper_2503_17743_amd import moc\n"
+            "moc.lib()\n"
+            "import torch, os\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "libs = sorted({l.split()[-1] for l in maps if 'libamdhip64' in l})\n"
+            "tdir = os.path.realpath(os.path.dirname(torch.__file__))\n"
+            "assert len(libs) == 1, libs\n"
+            "assert os.path.realpath(libs[0]).startswith(tdir), libs\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+
+
 def _plan_err(prob):
     with pytest.raises(moc.MocError) as e:
         moc.Plan(prob)
