@@ -10,7 +10,9 @@
  *     to the box, and then traced by BRUTE FORCE in 3D against every plane,
  *     circle and sector half-line they cross (no 2D segments, no Eqs. 6-11);
  *   - explicit segment storage, FP64 everywhere, exp via expm1;
- *   - Jacobi source iteration (Eq. 3 per segment, Eq. 4 estimator).
+ *   - Jacobi source iteration (Eq. 3 per segment, Eq. 4 estimator), with the
+ *     boundary flux either lagged one sweep or passed along whole chains of
+ *     reflected tracks within the sweep.
  *
  * Readings of points the paper leaves open (quadrature, laydown, chain phase,
  * link scheme, volumes, residual) are listed in the design notes and restated
@@ -40,7 +42,8 @@
  *   2 scattering matrix transposed           5 estimator without 4 pi qhat
  *   3 track weight without sin(theta)        6 volumes from one direction
  *   7 fission source without 1/k             8 azimuthal weights from the
- *                                              desired (uncorrected) angles */
+ *                                              desired (uncorrected) angles
+ *   9 chain sweep that drops the flux at every reflective crossing */
 #ifndef ORC_MUTATION
 #define ORC_MUTATION 0
 #endif
@@ -870,9 +873,84 @@ static int fsr_material(const struct orc_model *m, long long j) {
     return m->cell_mat[2 * cell + (inside ? 0 : 1)];
 }
 
+/* Eq. 3 along one directed 3D track: psi (the incoming flux on entry) leaves
+ * as the outgoing flux; acc += w * delta psi of every segment (Eq. 4). */
+static void track_sweep(const struct orc_model *m, long long dt, const double *qhat,
+                        const int *mat, double w, double *psi, double *acc) {
+    const int G = m->G;
+    long long tr = dt / 2;
+    int dir = (int)(dt % 2);
+    long long b = m->seg_off[tr], e = m->seg_off[tr + 1];
+    for (long long kk = 0; kk < e - b; ++kk) {
+        long long k = dir ? (e - 1 - kk) : (b + kk);
+        long long j = m->seg_fsr[k];
+        double l = m->seg_len[k];
+        int mm = mat[j];
+        for (int g = 0; g < G; ++g) {
+            double st = m->sigt[mm * G + g];
+            /* Eq. 3: psi_out = psi_in e^{-st l} + qhat (1 - e^{-st l}) */
+            double dpsi = (psi[g] - qhat[j * G + g]) * orc_atten(st * l);
+            acc[j * G + g] += w * dpsi;
+            psi[g] -= dpsi;
+        }
+    }
+}
+
+/* Chains of directed 3D tracks (the successor map followed from a track that
+ * no track continues into): the number of such heads, and the longest chain
+ * in tracks.  Returns 0, or -3 when some track lies on no chain (a closed
+ * loop: every face it meets is reflective) or on more than one. */
+static int chain_walk(const struct orc_model *m, long long *heads, long long *n_heads,
+                      long long *max_len) {
+    const long long ND = 2 * m->n3d;
+    char *has_pred = calloc(ND, 1), *seen = calloc(ND, 1);
+    long long nh = 0, longest = 0, visited = 0;
+    int rc = 0;
+    for (long long dt = 0; dt < ND; ++dt)
+        if (m->succ[dt] >= 0) has_pred[m->succ[dt]] = 1;
+    for (long long dt = 0; dt < ND && rc == 0; ++dt) {
+        if (has_pred[dt]) continue;
+        if (heads) heads[nh] = dt;
+        ++nh;
+        long long len = 0;
+        for (long long x = dt; x >= 0; x = m->succ[x]) {
+            if (seen[x]) { rc = -3; break; }
+            seen[x] = 1;
+            ++len;
+        }
+        visited += len;
+        if (len > longest) longest = len;
+    }
+    if (rc == 0 && visited != ND) rc = -3;
+    free(has_pred);
+    free(seen);
+    if (n_heads) *n_heads = nh;
+    if (max_len) *max_len = longest;
+    return rc;
+}
+
+int orc_chain_info(const orc_model *m, long long *n_heads, long long *max_len) {
+    if (!m->traced) return -2;
+    return chain_walk(m, NULL, n_heads, max_len);
+}
+
 int orc_solve(const orc_model *m, const double *q, double tol, int max_iters,
               double *phi_out, double *res_hist, orc_result *res) {
+    return orc_solve_ex(m, q, tol, max_iters, 0, 1, phi_out, res_hist, res);
+}
+
+int orc_solve_ex(const orc_model *m, const double *q, double tol, int max_iters, int chain,
+                 int inner, double *phi_out, double *res_hist, orc_result *res) {
     if (!m->traced) return -2;
+    if (inner < 1 || (chain && inner != 1)) return -1;
+    long long *heads = NULL, n_heads = 0;
+    if (chain) {
+        heads = malloc(sizeof(long long) * 2 * (size_t)m->n3d + 8);
+        if (chain_walk(m, heads, &n_heads, NULL) != 0) {
+            free(heads);
+            return -3;
+        }
+    }
     const int G = m->G;
     const long long NF = m->n_fsr, N3 = m->n3d, ND = 2 * N3;
     const double FOURPI = 4.0 * ORC_PI;
@@ -887,6 +965,7 @@ int orc_solve(const orc_model *m, const double *q, double tol, int max_iters,
     for (long long j = 0; j < NF; ++j) mat[j] = fsr_material(m, j);
     double residual = 1.0;
     int it;
+    long long n_sweeps = 0;
     orc_result r;
     memset(&r, 0, sizeof(r));
     for (it = 1; it <= max_iters; ++it) {
@@ -903,47 +982,59 @@ int orc_solve(const orc_model *m, const double *q, double tol, int max_iters,
                 qhat[j * G + g] = s / ((ORC_MUTATION == 1 ? 1.0 : FOURPI) * m->sigt[mm * G + g]);
             }
         }
+        /* Lagged mode: each sweep reads the boundary flux the previous
+         * sweep left (inner > 1 repeats the sweep with this source, keeping
+         * the last sweep's tallies).  Chain mode: every chain is swept from
+         * its head (a vacuum face, zero incoming flux) to its end, the
+         * outgoing flux of a track entering its successor at once, so no
+         * boundary flux is carried between iterations. */
+        for (int sw = 0; sw < inner; ++sw) {
         memset(acc_t, 0, sizeof(double) * (size_t)nth * NF * G);
         memset(tl_leak, 0, sizeof(double) * nth);
         memset(tl_in, 0, sizeof(double) * nth);
         memset(tl_out, 0, sizeof(double) * nth);
-        double *psi_in = (it % 2) ? psi_a : psi_b;
-        double *psi_out = (it % 2) ? psi_b : psi_a;
+        ++n_sweeps;
+        double *psi_in = (n_sweeps % 2) ? psi_a : psi_b;
+        double *psi_out = (n_sweeps % 2) ? psi_b : psi_a;
 #pragma omp parallel num_threads(nth)
         {
             int tid = omp_get_thread_num();
             double *acc = acc_t + (size_t)tid * NF * G;
             double psi[64];
             double my_in = 0.0, my_out = 0.0, my_leak = 0.0;
-#pragma omp for schedule(dynamic, 64)
-            for (long long dt = 0; dt < ND; ++dt) {
-                long long tr = dt / 2;
-                int dir = (int)(dt % 2);
-                double w = orc_track_weight(m, tr);
-                for (int g = 0; g < G; ++g) { psi[g] = psi_in[dt * G + g]; my_in += w * psi[g]; }
-                long long b = m->seg_off[tr], e = m->seg_off[tr + 1];
-                for (long long kk = 0; kk < e - b; ++kk) {
-                    long long k = dir ? (e - 1 - kk) : (b + kk);
-                    long long j = m->seg_fsr[k];
-                    double l = m->seg_len[k];
-                    int mm = mat[j];
-                    for (int g = 0; g < G; ++g) {
-                        double st = m->sigt[mm * G + g];
-                        /* Eq. 3: psi_out = psi_in e^{-st l} + qhat (1 - e^{-st l}) */
-                        double dpsi = (psi[g] - qhat[j * G + g]) * orc_atten(st * l);
-                        acc[j * G + g] += w * dpsi;
-                        psi[g] -= dpsi;
+            if (chain) {
+#pragma omp for schedule(dynamic, 16)
+                for (long long hh = 0; hh < n_heads; ++hh) {
+                    for (int g = 0; g < G; ++g) psi[g] = 0.0;
+                    for (long long dt = heads[hh]; dt >= 0; dt = m->succ[dt]) {
+                        double w = orc_track_weight(m, dt / 2);
+                        for (int g = 0; g < G; ++g) my_in += w * psi[g];
+                        track_sweep(m, dt, qhat, mat, w, psi, acc);
+                        for (int g = 0; g < G; ++g) my_out += w * psi[g];
+                        if (m->succ[dt] < 0)
+                            for (int g = 0; g < G; ++g) my_leak += w * psi[g];
+#if ORC_MUTATION == 9
+                        for (int g = 0; g < G; ++g) psi[g] = 0.0;
+#endif
                     }
                 }
-                long long nx = m->succ[dt];
-                for (int g = 0; g < G; ++g) my_out += w * psi[g];
-                if (nx >= 0) {
-                    for (int g = 0; g < G; ++g) psi_out[nx * G + g] = psi[g];
-                } else {
-                    for (int g = 0; g < G; ++g) my_leak += w * psi[g];
+            } else {
+#pragma omp for schedule(dynamic, 64)
+                for (long long dt = 0; dt < ND; ++dt) {
+                    double w = orc_track_weight(m, dt / 2);
+                    for (int g = 0; g < G; ++g) { psi[g] = psi_in[dt * G + g]; my_in += w * psi[g]; }
+                    track_sweep(m, dt, qhat, mat, w, psi, acc);
+                    long long nx = m->succ[dt];
+                    for (int g = 0; g < G; ++g) my_out += w * psi[g];
+                    if (nx >= 0) {
+                        for (int g = 0; g < G; ++g) psi_out[nx * G + g] = psi[g];
+                    } else {
+                        for (int g = 0; g < G; ++g) my_leak += w * psi[g];
+                    }
                 }
             }
             tl_in[tid] = my_in; tl_out[tid] = my_out; tl_leak[tid] = my_leak;
+        }
         }
         /* Eq. 4 estimator: phi = 4 pi qhat + sum W dpsi / (Sigma_t V) */
         double maxres = 0.0, bal_lhs = 0.0, absorb = 0.0, src = 0.0;
@@ -984,7 +1075,7 @@ int orc_solve(const orc_model *m, const double *q, double tol, int max_iters,
     memcpy(phi_out, phi, sizeof(double) * NF * G);
     if (res) *res = r;
     free(phi); free(qhat); free(psi_a); free(psi_b); free(acc_t); free(tl_leak); free(tl_in);
-    free(tl_out); free(mat);
+    free(tl_out); free(mat); free(heads);
     return 0;
 }
 

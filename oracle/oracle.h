@@ -107,6 +107,22 @@ int orc_volumes(const orc_model *m, double *vol);
 int orc_solve(const orc_model *m, const double *q, double tol, int max_iters,
               double *phi_out, double *res_hist, orc_result *res);
 
+/* orc_solve with a choice of boundary-flux coupling.  chain 0: the flux
+ * leaving a track enters its successor in the next sweep (Jacobi lag), and
+ * inner >= 1 sweeps run per source iteration with the same source, the last
+ * one's tallies giving the flux.  chain 1 (inner must be 1): each sweep
+ * follows every chain of reflected tracks from its head, a track whose
+ * start no other track continues into, with zero incoming flux, passing the
+ * flux to the successor within the sweep (characteristic lines swept whole,
+ * section 2.1, across reflective faces).  Returns -3 if some track lies on
+ * a closed loop of reflections (no vacuum face on its chain). */
+int orc_solve_ex(const orc_model *m, const double *q, double tol, int max_iters, int chain,
+                 int inner, double *phi_out, double *res_hist, orc_result *res);
+
+/* Number of chains of directed tracks and the longest chain (in tracks);
+ * -3 if a closed loop of reflections exists (traced build). */
+int orc_chain_info(const orc_model *m, long long *n_heads, long long *max_len);
+
 /* Eigenvalue mode: power iteration on k-eff with fission source chi_g F_j / k,
  * F_j = sum_g nu_sigma_f phi_j,g (nu_sigma_f, chi [M][G]).  From phi = 1,
  * psi = 0, k = 1; the residual is the larger of the relative change of k and

@@ -80,6 +80,9 @@ def lib():
         L.orc_segment_counts.argtypes = [C.c_void_p, C.c_void_p]
         L.orc_solve.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_int, C.c_void_p,
                                 C.c_void_p, P(_Result)]
+        L.orc_solve_ex.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_int, C.c_int, C.c_int,
+                                   C.c_void_p, C.c_void_p, P(_Result)]
+        L.orc_chain_info.argtypes = [C.c_void_p, P(C.c_longlong), P(C.c_longlong)]
         L.orc_solve_eigen.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int,
                                       C.c_void_p, P(C.c_double), C.c_void_p, P(_Result)]
         L.orc_sweep_sample.argtypes = [C.c_void_p, C.c_longlong, C.c_void_p, C.c_void_p,
@@ -228,7 +231,10 @@ class Model:
         return v
 
     # ---- solves -----------------------------------------------------------
-    def solve(self, q=None, tol=None, max_iters=None):
+    def solve(self, q=None, tol=None, max_iters=None, chain=False, inner=1):
+        """Source iteration (see orc_solve_ex): chain=False lags the boundary
+        flux one sweep (inner sweeps per source iteration), chain=True sweeps
+        whole chains of reflected tracks."""
         prob = self.prob
         q = np.ascontiguousarray(prob.q if q is None else q, dtype=np.float64)
         tol = prob.tol if tol is None else tol
@@ -236,13 +242,21 @@ class Model:
         phi = np.zeros((self.info["n_fsr"], prob.n_groups))
         hist = np.zeros(max_iters)
         r = _Result()
-        rc = lib().orc_solve(self._h, _ptr(q), float(tol), int(max_iters), _ptr(phi), _ptr(hist),
-                             C.byref(r))
+        rc = lib().orc_solve_ex(self._h, _ptr(q), float(tol), int(max_iters), int(bool(chain)),
+                                int(inner), _ptr(phi), _ptr(hist), C.byref(r))
         if rc != 0:
             raise ValueError(f"oracle solve failed: {rc}")
         res = {f: getattr(r, f) for f, _ in _Result._fields_}
         res["residual_history"] = hist[:r.iters].copy()
         return phi, res
+
+    def chain_info(self):
+        """(number of chains of directed tracks, longest chain in tracks)."""
+        nh, ml = C.c_longlong(), C.c_longlong()
+        rc = lib().orc_chain_info(self._h, C.byref(nh), C.byref(ml))
+        if rc != 0:
+            raise ValueError(f"oracle chain_info failed: {rc}")
+        return nh.value, ml.value
 
     def solve_eigen(self, nu_sigma_f, chi, tol=1e-8, max_iters=1000):
         """Power iteration on k-eff (see orc_solve_eigen); returns

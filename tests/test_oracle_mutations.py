@@ -1,7 +1,7 @@
 """The pins catch plausible mistakes: the oracle is rebuilt with one planted
 mistake at a time (a slip in the reduced source, the scattering orientation,
 the track weight, the attenuation, the estimator, the volumes, the
-fission source or the azimuthal weights) and the pin
+fission source, the azimuthal weights or the chain sweep) and the pin
 suite must fail for every one of them."""
 import os
 import subprocess
@@ -22,6 +22,7 @@ MUTATIONS = {
     6: "volumes from one sweep direction",
     7: "fission source without 1/k (eigenvalue mode)",
     8: "azimuthal weights from the desired angles",
+    9: "chain sweep that drops the flux at reflective crossings",
 }
 
 

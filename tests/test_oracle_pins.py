@@ -373,6 +373,68 @@ def test_slab_escape_probability(tau, n_polar):
     assert abs(p_moc - exact) < 2 * abs(gl - exact) + 1e-4 * exact
 
 
+@pytest.mark.parametrize("tau,n_polar,n_layers", [(0.05, 4, 3), (0.7, 6, 4), (3.0, 6, 5), (2.0, 8, 6)])
+def test_chain_sweep_slab_profile(tau, n_polar, n_layers):
+    """Chain mode, one sweep, pure absorber in a slab (reflective sides, vacuum
+    top and bottom): every chain of reflected tracks is one straight line from
+    one z face to the other, so the flux along it is qhat (1 - e^{-Sigma_t z /
+    |mu|}) with z measured from its entry face, and each layer's flux is that
+    profile's layer average summed over the discrete directions (corrected
+    polar cosines, weights dphi x w).  The lagged mode's first sweep, whose
+    side-face fluxes are still zero, is far from it."""
+    H = 2.0
+    sig = tau / H
+    p = P.pure_absorber(n_groups=1, sigma=(sig,), q=[1.0], bc=(1, 1, 1, 1, 0, 0), nx=1,
+                        pitch=1.5, height=H, n_layers=n_layers, n_azim=8, n_polar=n_polar,
+                        radial=0.05, axial=0.05, max_iters=1)
+    m = O.Model(p)
+    phi, _ = m.solve(tol=0.0, max_iters=1, chain=True)
+    lagged, _ = m.solve(tol=0.0, max_iters=1)
+    q = m.quadrature()
+    c = np.abs(q["cot"])
+    mu = c / np.sqrt(1 + c * c)
+    w = q["dphi"][:, None] * q["wpol"][None, :]
+    qhat = 1.0 / (4 * math.pi * sig)
+    h = H / n_layers
+    z = np.arange(n_layers + 1) * h
+
+    def layer_mean(z0, z1):      # mean of 1 - e^{-sig z/mu} over [z0, z1]
+        return 1 - mu / (sig * h) * (np.exp(-sig * z0 / mu) - np.exp(-sig * z1 / mu))
+
+    exact = np.array([qhat * np.sum(w * (layer_mean(z[k], z[k + 1]) + layer_mean(H - z[k + 1], H - z[k])))
+                      for k in range(n_layers)])
+    np.testing.assert_allclose(phi[:, 0], exact, rtol=1e-11)
+    assert np.min(np.abs(lagged[:, 0] - exact) / exact) > 0.05
+
+
+def test_chain_sweep_is_the_lagged_sweep_repeated_to_the_chain_depth(small):
+    """With the source frozen, the lagged sweep repeated as many times as the
+    longest chain has tracks carries the exact flux into every track, so its
+    last sweep equals one chain sweep; one repetition fewer does not."""
+    p, m = small
+    n_chains, depth = m.chain_info()
+    assert n_chains > 0 and depth >= 2
+    for iters in (1, 3):
+        chain, rc = m.solve(tol=0.0, max_iters=iters, chain=True)
+        deep, rd = m.solve(tol=0.0, max_iters=iters, inner=depth)
+        short, _ = m.solve(tol=0.0, max_iters=iters, inner=depth - 1)
+        np.testing.assert_allclose(chain, deep, rtol=1e-12, atol=0)
+        assert abs(rc["leakage"] - rd["leakage"]) < 1e-12 * rd["leakage"]
+        assert np.max(np.abs(short - chain) / np.abs(chain)) > 1e-8
+
+
+def test_chain_and_lagged_share_the_fixed_point(small):
+    """Passing the flux along chains changes the iterates, not the solution:
+    both couplings converge to the same flux, and the chain iteration, without
+    the lag, in fewer iterations."""
+    p, m = small
+    chain, rc = m.solve(tol=1e-12, max_iters=400, chain=True)
+    lagged, rl = m.solve(tol=1e-12, max_iters=400)
+    np.testing.assert_allclose(chain, lagged, rtol=1e-10, atol=0)
+    assert rc["iters"] < rl["iters"]
+    assert abs(rc["absorption"] + rc["leakage"] - rc["source"]) < 1e-9 * rc["source"]
+
+
 def test_per_iteration_balance(small):
     """sum_j,g acc = sum W psi_in(k-1) - sum W psi_out(k) at every iterate, and
     absorption + leakage = source at convergence."""
