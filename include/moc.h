@@ -276,10 +276,25 @@ MOC_API int moc_solver_set_schedule(moc_solver *s, int order, int persistent);
  * how the waves of a workgroup share the 64-line bundles of a window.
  * mode 0 = static (wave w takes bundles w, w + waves, ...); 1 = dynamic (a
  * wave that finishes a bundle takes the next one not yet taken); -1 =
- * automatic (dynamic in 1024-thread workgroups, static otherwise; the
- * default).  Only which wave sweeps which lines changes, so results agree
+ * automatic (dynamic from an estimated 4 bundles per wave in the window,
+ * static below; the default).  Only which wave sweeps which lines changes, so results agree
  * up to the order of the FP64 tally additions.  EINVAL for other values. */
 MOC_API int moc_solver_set_bundles(moc_solver *s, int mode);
+
+/* Chain-line sweeping (section 2.1: Eqs. 2-4 solved along whole
+ * characteristic lines; section 2.2: the z-stack lines of Eq. 5 continued
+ * across the reflective side faces).  on = 1: each sweep follows every line
+ * from the z face it enters through to the one it leaves through, the flux
+ * leaving a track through a side face entering the reflected track within
+ * the same sweep, instead of one sweep later through the boundary buffers
+ * (the default, on = 0).  The fixed point is the same; the iterates differ
+ * (no lag).  One workgroup sweeps one directed 2D cycle for one polar angle,
+ * unit after unit, so the sweep has far less parallelism.  Needs vacuum top
+ * and bottom faces, an even polar count and the per-lane FP32 sweep (at
+ * most 8 groups); EINVAL otherwise, and moc_solve / moc_iterate /
+ * moc_solve_eigen return EINVAL in chain mode with options that select
+ * another sweep (FP64 or the naive exponential).  Drops captured steps. */
+MOC_API int moc_solver_set_chain(moc_solver *s, int on);
 
 /* Eigenvalue mode: power iteration on k-eff (the multiplication factor the
  * paper's validation reports, Table 2).  nu_sigma_f and chi are [M][G]

@@ -212,6 +212,15 @@ int moc_solver_set_bundles(moc_solver *sv, int mode) {
     return MOC_OK;
 }
 
+int moc_solver_set_chain(moc_solver *sv, int on) {
+    if (!sv) return fail(MOC_EINVAL, "NULL solver");
+    if (on != 0 && on != 1) return fail(MOC_EINVAL, "on must be 0 or 1");
+    if (sv->s.set_chain(on))
+        return fail(MOC_EINVAL, "the chain-line sweep needs vacuum top and bottom faces, an even polar "
+                                "count and the per-lane FP32 sweep (at most 8 groups)");
+    return MOC_OK;
+}
+
 int moc_solver_set_window(moc_solver *sv, int threads) {
     if (!sv) return fail(MOC_EINVAL, "NULL solver");
     if (threads != 0 && threads != 256 && threads != 512 && threads != 1024)

@@ -62,6 +62,19 @@ struct WinArgs {
     const unsigned *exp_tbase;       // first step-table entry of each unit of the launch
     unsigned *exp_table;             // per (unit, window, bundle): steps, then their exclusive prefix
     Piece *exp_data;                 // recorded pieces [wave step][64 lanes]
+    // chain-line sweep: workgroup b sweeps traversal b / chain_classes, the
+    // stacks of polar class b mod chain_classes (|cot| index: stacks n and
+    // P - 1 - n), item by item (see Plan::ch_*)
+    int chain_classes;
+    const int *chain_first, *chain_code, *chain_pass;
+    const double *chain_spos, *chain_lc;
+};
+
+// The lines of one chain-sweep item: polar class, pass, the unit's unrolled
+// start along its traversal and the traversal's length.
+struct ChainItem {
+    int cls, pass;
+    double spos, lc;
 };
 
 // Per-problem control of a batched step: the stopping rule and the state the

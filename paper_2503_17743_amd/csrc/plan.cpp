@@ -477,6 +477,69 @@ std::string Plan::build(const moc_geometry &g, const moc_tracking &t, const moc_
     }
     n3d = trk_off[n_stacks];
     n_chunks = chunk_off[n_stacks];
+
+    // ------------------------------------------------ chain-line traversals
+    // With vacuum top and bottom faces every z-stack line, continued across
+    // the reflective side faces (Eq. 5 along the cycle), runs from one z face
+    // to the other, so a sweep can follow it whole.  Each directed cycle is
+    // walked from its chain origin (the start of the track C runs forward
+    // from chain position 0), where every line of every stack sits at
+    // z = (i + 1/2) dz: the pass boundaries (a line's 2D distance from its
+    // entry face to the origin, a multiple of the cycle length) then fall
+    // half a spacing away from every line.  A line rising by at most H over
+    // a 2D distance of H / min|cot| reaches past the origin into pass p only
+    // at units starting before H / min|cot| - (p - 1) L_C.
+    n_trav = 0;
+    ch_first.assign(1, 0);
+    ch_code.clear();
+    ch_pass.clear();
+    ch_spos.clear();
+    ch_lc.clear();
+    if (bc[MOC_FACE_ZMIN] == MOC_BC_VACUUM && bc[MOC_FACE_ZMAX] == MOC_BC_VACUUM) {
+        std::vector<int64_t> units;
+        std::vector<double> spos;
+        for (int64_t t0 = 0; t0 < n2d; ++t0) {
+            if (!(sig[t0] == 1 && chain[t0] == 0.0)) continue;
+            double cmin = 0.0;
+            for (int n = 0; n < P; ++n) {
+                const double c = std::fabs(cot[az[t0] * P + n]);
+                if (n == 0 || c < cmin) cmin = c;
+            }
+            for (int rev = 0; rev < 2; ++rev) {
+                const int64_t start = rev ? link[2 * t0 + 1] : 2 * t0;
+                units.clear();
+                spos.clear();
+                double pos = 0.0;
+                int64_t u = start;
+                do {
+                    units.push_back(u);
+                    spos.push_back(pos);
+                    pos += L[u / 2];
+                    u = link[u];
+                    if ((int64_t)units.size() > 2 * n2d) return "internal: traversal does not close";
+                } while (u != start);
+                const double lc = pos, reach = H / cmin;
+                for (int pass = 0;; ++pass) {
+                    const double lim = reach - (pass - 1) * lc;
+                    size_t added = 0;
+                    for (size_t j = 0; j < units.size(); ++j)
+                        if (pass == 0 || spos[j] < lim) {
+                            ch_code.push_back((int)units[j]);
+                            ch_pass.push_back(pass);
+                            ch_spos.push_back(spos[j]);
+                            ++added;
+                        }
+                    if (added == 0) break;
+                }
+                ch_lc.push_back(lc);
+                ch_first.push_back((int)ch_code.size());
+                ++n_trav;
+            }
+        }
+        int64_t covered = 0;
+        for (int64_t i = 0; i < (int64_t)ch_code.size(); ++i) covered += ch_pass[i] == 0;
+        if (covered != 2 * n2d) return "internal: traversals do not cover every unit";
+    }
     return "";
 }
 
@@ -544,6 +607,11 @@ Layout make_layout(const Plan &p, bool psi64) {
     l.off_psi1 = take(psi);
     l.psi_bytes = 2 * ((psi + 255) & ~size_t(255));
     l.off_work = take((size_t)2 * p.n2d * 4);
+    l.off_ch_first = take((p.n_trav + 1) * 4);
+    l.off_ch_code = take(p.ch_code.size() * 4 + 4);
+    l.off_ch_pass = take(p.ch_pass.size() * 4 + 4);
+    l.off_ch_spos = take(p.ch_spos.size() * 8 + 8);
+    l.off_ch_lc = take(p.n_trav * 8 + 8);
     l.off_scal = take(128 * 1024);
     l.off_nusf = take((size_t)p.M * p.G * 8);
     l.off_chi = take((size_t)p.M * p.G * 8);

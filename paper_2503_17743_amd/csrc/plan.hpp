@@ -66,6 +66,18 @@ struct Plan {
     std::vector<double> zeta;
     std::vector<int64_t> ilo, cnt, trk_off, chunk_off;   // trk_off/chunk_off: [n_stacks+1]
 
+    // ---- chain-line sweep (vacuum top and bottom faces only) ----
+    // A traversal is a directed 2D cycle, its units (2*t + dir) in link order
+    // from the cycle's chain origin.  Its items are the units of pass 0, then
+    // of the later passes those that lines wrapping past the origin reach:
+    // unit code, pass and the unit's start as unrolled 2D position along the
+    // traversal; ch_lc is each traversal's length.
+    int64_t n_trav = 0;
+    std::vector<int> ch_first;                 // [n_trav+1] item range of each traversal
+    std::vector<int> ch_code, ch_pass;         // [items]
+    std::vector<double> ch_spos;               // [items]
+    std::vector<double> ch_lc;                 // [n_trav]
+
     std::string build(const moc_geometry &g, const moc_tracking &t, const moc_xs &x);
     moc_plan_info info() const;
 };
@@ -91,6 +103,7 @@ struct Layout {
     size_t off_units = 0, off_filt_n = 0, off_filt_i0 = 0;
     size_t n_item_cap = 0, scratch_bytes = 0;
     size_t off_work = 0;            // windowed-sweep work list (2 * n2d codes)
+    size_t off_ch_first = 0, off_ch_code = 0, off_ch_pass = 0, off_ch_spos = 0, off_ch_lc = 0;
     bool psi64 = false;             // boundary angular flux stored in FP64
 };
 

@@ -101,6 +101,12 @@ struct Solver {
     // 0 static (wave w takes w, w + waves, ...), 1 dynamic (an LDS counter)
     int bundles = -1;
     bool dyn_bundles() const;
+    // chain-line sweep: the flux leaving a line through a reflective side
+    // face enters its continuation within the same sweep (vacuum top and
+    // bottom faces; the per-lane FP32 sweep only)
+    int chain = 0;
+    int64_t n_trav = 0;
+    int set_chain(int on);
     int upload_work_list();
     // stored-segment (EXP) sweep (paper section 4.2): the recorded pieces of
     // the units with the most pieces, replayed; the other units on the fly

@@ -485,7 +485,8 @@ __device__ inline double uniform_val(double v) {
 template <typename R, typename B, int MODE, int EXPM, bool BWD, bool C1, int GC = 0, bool LANE = false,
           int NT = kWinThreads, int EXP = 0>
 __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit,
-                                           unsigned char *smem, bool flip = false) {
+                                           unsigned char *smem, bool flip = false,
+                                           const ChainItem *ci = nullptr) {
     static_assert(!LANE || (MODE == 0 && C1), "the per-lane walk is the one-chunk transport sweep");
     static_assert(EXP == 0 || LANE, "the stored-segment sweep records the per-lane walk");
     // the transport arithmetic runs in the on-the-fly sweep and in the replay
@@ -587,7 +588,36 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
         }
     };
     const int n_srch = lane;
-    const bool srch = wave == 0 && n_srch < P && (fn < 0 || fn == n_srch);
+    // chain sweep: only the stacks of the item's polar class
+    const bool srch = wave == 0 && n_srch < P && (fn < 0 || fn == n_srch) &&
+                      (!ci || min(n_srch, P - 1 - n_srch) == ci->cls);
+    // Chain sweep: the lines of this stack the item's pass sweeps.  A line
+    // rising (falling) along the traversal that is at z (at H - z) where this
+    // unit starts entered through the bottom (top) face a 2D distance z / |cot|
+    // before; with x that distance minus the unit's unrolled start, pass p
+    // takes the lines with (p - 1) L_C < x <= p L_C (lines entering inside
+    // the unit have x < 0, pass 0).  The bounds fall half a spacing from
+    // every line (the traversals start where all lines sit at (i + 1/2) dz),
+    // so the closed forms need no check.
+    int ch_lo = 0, ch_hi = 0x7fffffff;
+    if (ci && srch) {
+        const long long s = t * P + n_srch;
+        const double c = a.cot[az * P + n_srch];
+        const double ce = dir ? -c : c;
+        const double z0 = a.zeta[s] + (double)a.ilo[s] * a.dz + c * (dir ? Lt : 0.0);
+        const double x0 = (ci->pass - 1) * ci->lc + ci->spos, x1 = ci->pass * ci->lc + ci->spos;
+        const double cnt_s = (double)a.cnt[s];
+        double flo, fhi;
+        if (ce > 0) {
+            flo = floor((ce * x0 - z0) * a.inv_dz) + 1.0;
+            fhi = floor((ce * x1 - z0) * a.inv_dz);
+        } else {
+            flo = ceil((a.H + ce * x1 - z0) * a.inv_dz);
+            fhi = ceil((a.H + ce * x0 - z0) * a.inv_dz) - 1.0;
+        }
+        ch_lo = (int)fmin(fmax(flo, 0.0), cnt_s);
+        ch_hi = (int)fmin(fmax(fhi, -1.0), cnt_s - 1.0);
+    }
     // wave 0: which lines of each polar stack cross window wi (a contiguous
     // index range, since line extents move monotonically with the line
     // index), and the bundle prefix over the stacks, into the line-range area
@@ -648,8 +678,8 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                 b0 = -1;
                 while (b0 < b1) { int m = (b0 + b1 + 1) >> 1; if (falling(m)) b0 = m; else b1 = m - 1; }
             }
-            lo = a0;
-            hi = b0;
+            lo = max(a0, ch_lo);
+            hi = min(b0, ch_hi);
             if (fn >= 0) {
                 lo = max(lo, (int)fi0);
                 hi = min(hi, (int)fi0 + T - 1);
@@ -1241,6 +1271,49 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     }
 }
 
+// Chain-line sweep (vacuum top and bottom faces): workgroup b follows one
+// traversal, a directed 2D cycle, for one polar class, sweeping its items in
+// order: every unit of pass 0, then the units that lines wrapping past the
+// traversal's origin reach in later passes.  The flux a line leaves through
+// a side face goes to its continuation's slot of the one boundary buffer,
+// which a later item of the same workgroup reads, so every line is swept
+// whole within the sweep (no flux lags an iteration).  The traversals of a
+// problem and their polar classes are independent.
+template <typename B, int GC, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_win_chain(WinArgs wa) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tv = blockIdx.x / wa.chain_classes;
+    ChainItem ci;
+    ci.cls = blockIdx.x - tv * wa.chain_classes;
+    ci.lc = wa.chain_lc[tv];
+    const int i1 = wa.chain_first[tv + 1];
+    for (int i = wa.chain_first[tv]; i < i1; ++i) {
+        const int code = wa.chain_code[i];
+        ci.pass = wa.chain_pass[i];
+        ci.spos = wa.chain_spos[i];
+        if (code & 1) sweep_unit<float, B, 0, 0, true, true, GC, true, NT>(wa, code, blockIdx.x, smem, false, &ci);
+        else sweep_unit<float, B, 0, 0, false, true, GC, true, NT>(wa, code, blockIdx.x, smem, false, &ci);
+        // the fluxes handed to the next units are read by any wave of this
+        // workgroup in a later item
+        __threadfence();
+        __syncthreads();
+    }
+}
+
+template <typename B, int NT>
+static void launch_chain(const WinArgs &wa, unsigned nb, size_t lds, hipStream_t st) {
+    switch (wa.s.G) {
+    case 1: k_sweep_win_chain<B, 1, NT><<<nb, NT, lds, st>>>(wa); break;
+    case 2: k_sweep_win_chain<B, 2, NT><<<nb, NT, lds, st>>>(wa); break;
+    case 3: k_sweep_win_chain<B, 3, NT><<<nb, NT, lds, st>>>(wa); break;
+    case 4: k_sweep_win_chain<B, 4, NT><<<nb, NT, lds, st>>>(wa); break;
+    case 5: k_sweep_win_chain<B, 5, NT><<<nb, NT, lds, st>>>(wa); break;
+    case 6: k_sweep_win_chain<B, 6, NT><<<nb, NT, lds, st>>>(wa); break;
+    case 7: k_sweep_win_chain<B, 7, NT><<<nb, NT, lds, st>>>(wa); break;
+    default: k_sweep_win_chain<B, 8, NT><<<nb, NT, lds, st>>>(wa); break;
+    }
+}
+
 // Store pass of the stored-segment sweep (wa.exp_pass 1 count, 2 step table,
 // 3 record): the per-lane walk's geometry only, for any G <= 8.
 template <int NT>
@@ -1828,6 +1901,12 @@ int Solver::upload(const Plan &p) {
     HIPCHK(put(lay.off_cnt, cnt.data(), cnt.size() * 4));
     HIPCHK(put(lay.off_trk_off, p.trk_off.data(), p.trk_off.size() * 8));
     HIPCHK(put(lay.off_chunk_off, p.chunk_off.data(), p.chunk_off.size() * 8));
+    HIPCHK(put(lay.off_ch_first, p.ch_first.data(), p.ch_first.size() * 4));
+    HIPCHK(put(lay.off_ch_code, p.ch_code.data(), p.ch_code.size() * 4));
+    HIPCHK(put(lay.off_ch_pass, p.ch_pass.data(), p.ch_pass.size() * 4));
+    HIPCHK(put(lay.off_ch_spos, p.ch_spos.data(), p.ch_spos.size() * 8));
+    HIPCHK(put(lay.off_ch_lc, p.ch_lc.data(), p.ch_lc.size() * 8));
+    n_trav = p.n_trav;
     HIPCHK(put(lay.off_sigt32, sigt32.data(), sigt32.size() * 4));
     HIPCHK(put(lay.off_sigt64, p.sigt.data(), p.sigt.size() * 8));
     HIPCHK(put(lay.off_sigs, p.sigs.data(), p.sigs.size() * 8));
@@ -2072,6 +2151,18 @@ void Solver::choose_lane_window() {
     }
 }
 
+int Solver::set_chain(int on) {
+    if (on) {
+        // vacuum top and bottom (every line ends on a z face), and the
+        // per-lane FP32 sweep (one group chunk)
+        if (n_trav == 0 || group_chunks(info.n_groups) != 1 || lane_win < 1 || (P % 2) != 0)
+            return MOC_EINVAL;
+    }
+    chain = on ? 1 : 0;
+    drop_step_graphs();
+    return MOC_OK;
+}
+
 int Solver::set_window(int threads) {
     if (threads == 256 && sw256 < 1) return MOC_EINVAL;
     if (threads == kWinThreadsBig && sw1024 < 1) return MOC_EINVAL;
@@ -2100,6 +2191,30 @@ void Solver::launch_sweep(SweepArgs a, bool fp64, const int *units, int n_units,
     // the per-lane walk runs in its own workgroup size and window
     const bool lane = !fp64 && a.mode == 0 && a.exp_mode == 0 && walk == 1 && lane_win >= 1;
     if (lane) sw = lane_win;
+    if (!units && chain && lane_path(a, fp64)) {
+        // chain-line sweep: one boundary buffer, read after its writer
+        WinArgs wa = lane_args(a);
+        wa.s.psi_out = wa.s.psi_in;
+        wa.chain_classes = P / 2;
+        wa.chain_first = ws_ptr<int>(ws, lay.off_ch_first);
+        wa.chain_code = ws_ptr<int>(ws, lay.off_ch_code);
+        wa.chain_pass = ws_ptr<int>(ws, lay.off_ch_pass);
+        wa.chain_spos = ws_ptr<double>(ws, lay.off_ch_spos);
+        wa.chain_lc = ws_ptr<double>(ws, lay.off_ch_lc);
+        const unsigned nb = (unsigned)(n_trav * wa.chain_classes);
+        if (nb == 0) return;
+        const size_t lds = win_lds_bytes(wa.Sw, K, info.n_groups, 4);
+        if (lay.psi64) {
+            if (wa.small_wg) launch_chain<double, 256>(wa, nb, lds, stream);
+            else if (wa.big_wg) launch_chain<double, kWinThreadsBig>(wa, nb, lds, stream);
+            else launch_chain<double, kWinThreads>(wa, nb, lds, stream);
+        } else {
+            if (wa.small_wg) launch_chain<float, 256>(wa, nb, lds, stream);
+            else if (wa.big_wg) launch_chain<float, kWinThreadsBig>(wa, nb, lds, stream);
+            else launch_chain<float, kWinThreads>(wa, nb, lds, stream);
+        }
+        return;
+    }
     if (!units && lane_path(a, fp64) && (exp_units > 0 || persistent)) {
         // stored-segment sweep: the stored units replayed, then the rest on
         // the fly (two launches in order on the stream); or a persistent grid
@@ -2426,6 +2541,8 @@ int Solver::reset() {
 }
 
 int Solver::iterate(int nit, const moc_solve_opts &o, bool time_sweep) {
+    // the chain-line sweep runs only in the per-lane FP32 transport sweep
+    if (chain && !lane_path(sweep_args(o.sweep_fp64, o.exp_mode), o.sweep_fp64 != 0)) return MOC_EINVAL;
     const FsrArgs f = fsr_args();
     const long long nfg = f.n;
     const unsigned fblocks = (unsigned)((nfg + 255) / 256);
@@ -2470,6 +2587,8 @@ void Solver::drop_step_graphs() {
 }
 
 int Solver::solve_step(const moc_solve_opts &o, double *res) {
+    // the chain-line sweep runs only in the per-lane FP32 transport sweep
+    if (chain && !lane_path(sweep_args(o.sweep_fp64, o.exp_mode), o.sweep_fp64 != 0)) return MOC_EINVAL;
     const int key = (o.sweep_fp64 ? 1 : 0) | (o.exp_mode ? 2 : 0) | (walk << 2);
     if (!h_res) HIPCHK(hipHostMalloc((void **)&h_res, 64, hipHostMallocDefault));
     for (int b = 0; b < 2; ++b)
@@ -2587,6 +2706,8 @@ int Solver::read_stats(moc_stats *st) {
 // the normalised fission source (1 at the first iteration).
 int Solver::solve_eigen(const double *nusf, const double *chi, const moc_solve_opts &o, double *k_out,
                         double *res_out, int *iters_out) {
+    // the chain-line sweep runs only in the per-lane FP32 transport sweep
+    if (chain && !lane_path(sweep_args(o.sweep_fp64, o.exp_mode), o.sweep_fp64 != 0)) return MOC_EINVAL;
     const int G = info.n_groups;
     const size_t mg = (size_t)n_materials * G;
     double *d_nusf = ws_ptr<double>(ws, lay.off_nusf), *d_chi = ws_ptr<double>(ws, lay.off_chi);

@@ -112,6 +112,7 @@ def lib():
         "moc_solver_set_schedule": ([VP, C.c_int, C.c_int], C.c_int),
         "moc_solver_set_window": ([VP, C.c_int], C.c_int),
         "moc_solver_set_bundles": ([VP, C.c_int], C.c_int),
+        "moc_solver_set_chain": ([VP, C.c_int], C.c_int),
         "moc_solver_window": ([VP, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
         "moc_iterate": ([VP, C.c_int, C.POINTER(SolveOpts), C.POINTER(Stats)], C.c_int),
         "moc_get_flux": ([VP, VP, C.c_size_t], C.c_int),
@@ -358,6 +359,12 @@ class Solver:
         """How a workgroup's waves share a window's bundles: static (wave w
         takes w, w + waves, ...), dynamic (the next untaken one), or auto."""
         _check(lib().moc_solver_set_bundles(self._h, self.BUNDLES[mode]))
+
+    def set_chain(self, on=True):
+        """Chain-line sweeping (moc_solver_set_chain): every line swept whole
+        from the z face it enters through to the one it leaves through, the
+        flux crossing reflective side faces within the sweep."""
+        _check(lib().moc_solver_set_chain(self._h, 1 if on else 0))
 
     def set_window(self, threads=0):
         """Workgroup size of the per-lane sweep: 0 (automatic), 256, 512, 1024."""

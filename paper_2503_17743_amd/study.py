@@ -19,6 +19,9 @@
   python -m paper_2503_17743_amd.study bundles [--workload lattice32] [--iters 5]
       Median sweep time with static and with dynamic assignment of a window's
       bundles to the waves, for each workgroup size, in interleaved rounds.
+  python -m paper_2503_17743_amd.study chain [--workload lattice8] [--iters 5] [--tol 1e-6]
+      Lagged against chain-line sweeping: median sweep time of each, and (with
+      --tol > 0) the iterations and time each takes to converge.
 
 Progress goes to stderr.
 """
@@ -257,13 +260,56 @@ def bundles_study(name, iters=5, sizes=(256, 512, 1024), rounds=2):
     return out
 
 
+def chain_study(name, iters=5, tol=1e-6, max_iters=2000, sizes=(0,)):
+    """Lagged boundary flux against chain-line sweeping: median sweep time
+    over `iters` iterations of each (per workgroup size in `sizes`, 0 the
+    automatic one), then, with tol > 0, the source iterations and wall time
+    each needs to reach tol."""
+    import torch
+    prob = P.get(name)
+    plan = moc.Plan(prob)
+    out = {"study": "chain", "workload": name, "iterations": iters, "tol": tol, "rows": []}
+    s = moc.Solver(plan, fp64_boundary=False)
+    s.set_source(prob.q)
+    for nt in sizes:
+        s.set_window(nt)
+        for chain in (False, True):
+            s.set_chain(chain)
+            s.reset()
+            s.iterate(1, stats=False)
+            st = s.iterate(iters)
+            row = {"mode": "chain" if chain else "lagged", "threads": s.window()[0],
+                   "segments_per_window": s.window()[1], "sweep_ms_median": st["sweep_ms_median"],
+                   "seg_group_per_s": st["seg_group_updates"] / (st["sweep_ms_median"] * 1e-3)}
+            _log(f"chain {name}: {row}")
+            out["rows"].append(row)
+    s.set_window(0)
+    if tol > 0:
+        out["converge"] = []
+        for chain in (False, True):
+            s.set_chain(chain)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            phi, st = s.solve(tol=tol, max_iters=max_iters)
+            torch.cuda.synchronize()
+            row = {"mode": "chain" if chain else "lagged", "iters": st["iters"],
+                   "converged": st["converged"], "residual": st["residual"],
+                   "wall_s": time.perf_counter() - t0, "sweep_ms_median": st["sweep_ms_median"]}
+            _log(f"chain {name} converge: {row}")
+            out["converge"].append(row)
+        s.set_chain(False)
+    s.close()
+    return out
+
+
 def main(argv=None):
     import torch
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=("precision", "scale", "eigen", "exp", "window", "bundles"))
+    ap.add_argument("study", choices=("precision", "scale", "eigen", "exp", "window", "bundles", "chain"))
     ap.add_argument("--workload", default=None)
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--walk", choices=("auto", "lockstep", "lane"), default="auto")
+    ap.add_argument("--tol", type=float, default=1e-6)
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
     if args.study == "precision":
@@ -274,6 +320,8 @@ def main(argv=None):
         out = bundles_study(args.workload or "lattice32", args.iters or 5)
     elif args.study == "exp":
         out = exp_study(args.workload or "lattice8", args.iters or 10)
+    elif args.study == "chain":
+        out = chain_study(args.workload or "lattice8", args.iters or 5, tol=args.tol)
     elif args.study == "eigen":
         out = eigen(args.workload or "lattice8", max_iters=args.iters or 2000)
     else:
