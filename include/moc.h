@@ -113,6 +113,9 @@ typedef struct {
                                  /* FP64 sweep to keep full precision)             */
     int line_stride;           /* most lines between neighbouring lanes of a sweep */
                                /* bundle (lines per axial layer)                  */
+    size_t workspace_bytes_chain; /* bytes for a chain-only solver: no boundary    */
+                                  /* buffers (moc_solver_set_chain; 0: the plan has */
+                                  /* no vacuum top and bottom faces)                */
 } moc_plan_info;
 
 /* Solve controls.  sweep_fp64 = 1 runs segment arithmetic and angular flux in
@@ -191,10 +194,14 @@ MOC_API int moc_plan_chunk(const moc_plan *plan, long long chunk, long long *fir
 /* Bind a plan to a caller-owned device workspace and stream; uploads the plan
  * (2D segments, z-stack table, links, cross sections: the data section 3.1
  * moves to the GPU) and computes the track-estimated FSR volumes V_j of the
- * Eq. 4 estimator with one volume sweep.  ENOMEM when ws_bytes <
- * workspace_bytes.  With ws_bytes >= workspace_bytes_fp64 the boundary
- * angular flux is stored in FP64 (else FP32).  The plan may be destroyed
- * afterwards. */
+ * Eq. 4 estimator with one volume sweep.  With ws_bytes >=
+ * workspace_bytes_fp64 the boundary angular flux is stored in FP64, with
+ * ws_bytes >= workspace_bytes in FP32.  A workspace of at least
+ * workspace_bytes_chain (when that is nonzero) but less than workspace_bytes
+ * makes a chain-only solver: it holds no boundary buffers, sweeps in chain
+ * mode 2 (moc_solver_set_chain) and refuses to leave chain mode, as well as
+ * moc_sweep_items and moc_gather_boundary.  ENOMEM below that.  The plan may
+ * be destroyed afterwards. */
 MOC_API int moc_solver_create(const moc_plan *plan, void *dev_workspace, size_t ws_bytes,
                               void *stream, moc_solver **out);
 /* Lifetime only: NULL-safe; does not free the caller's workspace. */
@@ -288,8 +295,10 @@ MOC_API int moc_solver_set_bundles(moc_solver *s, int mode);
  * leaving a track through a side face entering the reflected track within
  * the same sweep, instead of one sweep later through the boundary buffers
  * (the default, on = 0).  The fixed point is the same; the iterates differ
- * (no lag).  One workgroup sweeps one directed 2D cycle for one polar angle,
- * unit after unit, so the sweep has far less parallelism.  Needs vacuum top
+ * (no lag).  One workgroup sweeps one directed 2D cycle for one polar angle
+ * (on = 1) or for the rising or the falling lines of one polar angle (on = 2,
+ * twice the workgroups), unit after unit, so the sweep has far less
+ * parallelism than the lagged one.  Needs vacuum top
  * and bottom faces, an even polar count and the per-lane FP32 sweep (at
  * most 8 groups); EINVAL otherwise, and moc_solve / moc_iterate /
  * moc_solve_eigen return EINVAL in chain mode with options that select

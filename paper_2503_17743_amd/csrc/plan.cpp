@@ -539,6 +539,8 @@ std::string Plan::build(const moc_geometry &g, const moc_tracking &t, const moc_
         int64_t covered = 0;
         for (int64_t i = 0; i < (int64_t)ch_code.size(); ++i) covered += ch_pass[i] == 0;
         if (covered != 2 * n2d) return "internal: traversals do not cover every unit";
+        ch_cap = 0;
+        for (int64_t s = 0; s < n_stacks; ++s) ch_cap = std::max(ch_cap, cnt[s]);
     }
     return "";
 }
@@ -561,6 +563,7 @@ moc_plan_info Plan::info() const {
     o.workspace_bytes = l.total;
     o.psi_bytes = l.psi_bytes;
     o.workspace_bytes_fp64 = make_layout(*this, true).total;
+    o.workspace_bytes_chain = n_trav > 0 ? l.off_psi0 : 0;
     return o;
 }
 
@@ -602,16 +605,13 @@ Layout make_layout(const Plan &p, bool psi64) {
     l.off_acc = take(nfg * 8);
     l.off_phi = take(nfg * 8);
     l.off_vol = take((size_t)p.n_fsr * 8);
-    size_t psi = (size_t)2 * p.n3d * p.G * (psi64 ? 8 : 4);
-    l.off_psi0 = take(psi);
-    l.off_psi1 = take(psi);
-    l.psi_bytes = 2 * ((psi + 255) & ~size_t(255));
     l.off_work = take((size_t)2 * p.n2d * 4);
     l.off_ch_first = take((p.n_trav + 1) * 4);
     l.off_ch_code = take(p.ch_code.size() * 4 + 4);
     l.off_ch_pass = take(p.ch_pass.size() * 4 + 4);
     l.off_ch_spos = take(p.ch_spos.size() * 8 + 8);
     l.off_ch_lc = take(p.n_trav * 8 + 8);
+    l.off_ch_carry = take((size_t)p.n_trav * p.P * 4 * (size_t)p.ch_cap * p.G * (psi64 ? 8 : 4));
     l.off_scal = take(128 * 1024);
     l.off_nusf = take((size_t)p.M * p.G * 8);
     l.off_chi = take((size_t)p.M * p.G * 8);
@@ -624,6 +624,12 @@ Layout make_layout(const Plan &p, bool psi64) {
     l.off_filt_n = take(l.n_item_cap * 4);
     l.off_filt_i0 = take(l.n_item_cap * 8);
     l.scratch_bytes = off - l.off_items;
+    // the two boundary angular-flux buffers last: a chain-only solver (which
+    // passes every flux within the sweep) stops short of them
+    size_t psi = (size_t)2 * p.n3d * p.G * (psi64 ? 8 : 4);
+    l.off_psi0 = take(psi);
+    l.off_psi1 = take(psi);
+    l.psi_bytes = 2 * ((psi + 255) & ~size_t(255));
     l.total = off;
     return l;
 }

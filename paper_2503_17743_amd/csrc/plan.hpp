@@ -77,6 +77,7 @@ struct Plan {
     std::vector<int> ch_code, ch_pass;         // [items]
     std::vector<double> ch_spos;               // [items]
     std::vector<double> ch_lc;                 // [n_trav]
+    int64_t ch_cap = 0;                        // lines of the largest stack
 
     std::string build(const moc_geometry &g, const moc_tracking &t, const moc_xs &x);
     moc_plan_info info() const;
@@ -104,6 +105,9 @@ struct Layout {
     size_t n_item_cap = 0, scratch_bytes = 0;
     size_t off_work = 0;            // windowed-sweep work list (2 * n2d codes)
     size_t off_ch_first = 0, off_ch_code = 0, off_ch_pass = 0, off_ch_spos = 0, off_ch_lc = 0;
+    // chain sweep carry buffers: per workgroup (n_trav * P at most) two
+    // parities x two stacks x ch_cap lines x G fluxes of the boundary type
+    size_t off_ch_carry = 0;
     bool psi64 = false;             // boundary angular flux stored in FP64
 };
 

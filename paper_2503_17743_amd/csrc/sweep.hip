@@ -250,10 +250,21 @@ __device__ inline bool is_vacuum(const SweepArgs &a, const Bound &b) {
 // taken from the cyclic links; through an edge both apply.  The line index on
 // the successor's z-stack follows from matching z at the shared point (Eq. 5).
 // Returns -1 if no such line exists.
+__device__ inline long long successor_line(const SweepArgs &a, const Bound &b, long long t, int n,
+                                           int dir, double base, double c, int &n2, long long &i2);
 __device__ inline long long successor_slot(const SweepArgs &a, const Bound &b, long long t, int n,
                                            int dir, double base, double c) {
+    int n2;
+    long long i2;
+    return successor_line(a, b, t, n, dir, base, c, n2, i2);
+}
+
+// The same, also giving the continuation's polar index n2 and line index i2
+// in its stack.
+__device__ inline long long successor_line(const SweepArgs &a, const Bound &b, long long t, int n,
+                                           int dir, double base, double c, int &n2, long long &i2) {
     long long t2;
-    int d2, n2;
+    int d2;
     double l2, z2;
     const int P = a.P;
     if (b.kind == 0) {
@@ -273,7 +284,7 @@ __device__ inline long long successor_slot(const SweepArgs &a, const Bound &b, l
     }
     const long long s2 = t2 * P + n2;
     const double c2 = a.cot[(a.t_meta[t2] & 0xffff) * P + n2];
-    const long long i2 = llrint((z2 - a.zeta[s2] - c2 * l2) * a.inv_dz) - a.ilo[s2];
+    i2 = llrint((z2 - a.zeta[s2] - c2 * l2) * a.inv_dz) - a.ilo[s2];
     if (i2 < 0 || i2 >= (long long)a.cnt[s2]) return -1;
     return 2 * (a.trk_off[s2] + i2) + d2;
 }
@@ -588,9 +599,13 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
         }
     };
     const int n_srch = lane;
-    // chain sweep: only the stacks of the item's polar class
+    // chain sweep: only the stacks of the item's polar class (|cot| index,
+    // times two with the lines rising and falling along the traversal apart:
+    // stack n rises when cot > 0, n >= P / 2, in a forward unit)
     const bool srch = wave == 0 && n_srch < P && (fn < 0 || fn == n_srch) &&
-                      (!ci || min(n_srch, P - 1 - n_srch) == ci->cls);
+                      (!ci || (ci->split ? (2 * min(n_srch, P - 1 - n_srch) + ((n_srch >= P / 2) != (dir == 1))
+                                            == ci->cls)
+                                         : min(n_srch, P - 1 - n_srch) == ci->cls));
     // Chain sweep: the lines of this stack the item's pass sweeps.  A line
     // rising (falling) along the traversal that is at z (at H - z) where this
     // unit starts entered through the bottom (top) face a 2D distance z / |cot|
@@ -678,8 +693,12 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                 b0 = -1;
                 while (b0 < b1) { int m = (b0 + b1 + 1) >> 1; if (falling(m)) b0 = m; else b1 = m - 1; }
             }
-            lo = max(a0, ch_lo);
-            hi = min(b0, ch_hi);
+            lo = a0;
+            hi = b0;
+            if (ci) {
+                lo = max(lo, ch_lo);
+                hi = min(hi, ch_hi);
+            }
             if (fn >= 0) {
                 lo = max(lo, (int)fi0);
                 hi = min(hi, (int)fi0 + T - 1);
@@ -930,7 +949,12 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
             }
             const bool starts = dir == 0 ? (ls >= wa_) : (le <= wb_);
             const bool ends = dir == 0 ? (le <= wb_) : (ls >= wa_);
-            const long long slot = 2 * (a.trk_off[s] + i) + dir;
+            // the line's flux between windows (and on entry): its boundary
+            // slot, or in the chain sweep its entry of the item's carry
+            // buffer (parity, stack of the class, line)
+            const long long slot = ci ? ((long long)(ci->par * 2 + (n >= P / 2)) * ci->cap + i)
+                                      : 2 * (a.trk_off[s] + i) + dir;
+            B *const cbuf = ci ? (B *)ci->carry : (B *)psi_in;
             const size_t hook = (size_t)unit * kItemStride + (size_t)(i - fi0) * G + g0;
             R psi[kGL];
 #pragma unroll
@@ -939,7 +963,7 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
             // what Eq. 3 yields directly, and the tally needs no multiply
             const R Wr = (R)W;
             if (MODE == 0 && kPhys && active) {
-                const B *pin = (const B *)psi_in + slot * G + g0;
+                const B *pin = cbuf + slot * G + g0;
                 if (!starts) {
                     // carried from the previous window (already scaled by W)
 #pragma unroll
@@ -1172,7 +1196,7 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
             flush_pending();
             if (MODE == 0 && kPhys && active) {
                 if (!ends) {
-                    B *pc = (B *)psi_in + slot * G + g0;            // carried to the next window
+                    B *pc = cbuf + slot * G + g0;                   // carried to the next window
 #pragma unroll
                     for (int j = 0; j < kGL; ++j)
                         if (j < ng) pc[j] = (B)psi[j];
@@ -1191,10 +1215,15 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                     const Bound b = boundary_of(base, c, ic, Lt, a.H, dir, true, meta);
                     if (is_vacuum(a, b)) {
                         leak += wpsi;
-                    } else if (psi_out) {
-                        const long long slot2 = successor_slot(a, b, t, n, dir, base, c);
+                    } else if (psi_out || ci) {
+                        int n2;
+                        long long i2;
+                        long long slot2 = successor_line(a, b, t, n, dir, base, c, n2, i2);
+                        // chain sweep: the continuation is swept by the next
+                        // item, from the other carry buffer
+                        if (ci && slot2 >= 0) slot2 = (long long)((ci->par ^ 1) * 2 + (n2 >= P / 2)) * ci->cap + i2;
                         if (slot2 >= 0) {
-                            B *po = (B *)psi_out + slot2 * G + g0;
+                            B *po = (ci ? (B *)ci->carry : (B *)psi_out) + slot2 * G + g0;
 #pragma unroll
                             for (int j = 0; j < kGL; ++j)
                                 if (j < ng) po[j] = (B)psi[j];
@@ -1274,10 +1303,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 // Chain-line sweep (vacuum top and bottom faces): workgroup b follows one
 // traversal, a directed 2D cycle, for one polar class, sweeping its items in
 // order: every unit of pass 0, then the units that lines wrapping past the
-// traversal's origin reach in later passes.  The flux a line leaves through
-// a side face goes to its continuation's slot of the one boundary buffer,
-// which a later item of the same workgroup reads, so every line is swept
-// whole within the sweep (no flux lags an iteration).  The traversals of a
+// traversal's origin reach in later passes (a later pass exists only when
+// the one before covered every unit, so a line's continuation is always in
+// the next item).  The flux a line leaves through a side face goes to its
+// continuation's entry of the workgroup's other carry buffer, which the
+// next item reads, so every line is swept whole within the sweep (no flux
+// lags an iteration) and no boundary buffer is needed.  The traversals of a
 // problem and their polar classes are independent.
 template <typename B, int GC, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_win_chain(WinArgs wa) {
@@ -1285,12 +1316,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const int tv = blockIdx.x / wa.chain_classes;
     ChainItem ci;
     ci.cls = blockIdx.x - tv * wa.chain_classes;
+    ci.split = wa.chain_classes == wa.s.P;
     ci.lc = wa.chain_lc[tv];
-    const int i1 = wa.chain_first[tv + 1];
-    for (int i = wa.chain_first[tv]; i < i1; ++i) {
+    ci.cap = wa.chain_cap;
+    ci.carry = (B *)wa.chain_carry + (size_t)blockIdx.x * 4 * wa.chain_cap * wa.s.G;
+    const int i0 = wa.chain_first[tv], i1 = wa.chain_first[tv + 1];
+    for (int i = i0; i < i1; ++i) {
         const int code = wa.chain_code[i];
         ci.pass = wa.chain_pass[i];
         ci.spos = wa.chain_spos[i];
+        ci.par = (i - i0) & 1;
         if (code & 1) sweep_unit<float, B, 0, 0, true, true, GC, true, NT>(wa, code, blockIdx.x, smem, false, &ci);
         else sweep_unit<float, B, 0, 0, false, true, GC, true, NT>(wa, code, blockIdx.x, smem, false, &ci);
         // the fluxes handed to the next units are read by any wave of this
@@ -1907,6 +1942,7 @@ int Solver::upload(const Plan &p) {
     HIPCHK(put(lay.off_ch_spos, p.ch_spos.data(), p.ch_spos.size() * 8));
     HIPCHK(put(lay.off_ch_lc, p.ch_lc.data(), p.ch_lc.size() * 8));
     n_trav = p.n_trav;
+    chain_cap = (int)p.ch_cap;
     HIPCHK(put(lay.off_sigt32, sigt32.data(), sigt32.size() * 4));
     HIPCHK(put(lay.off_sigt64, p.sigt.data(), p.sigt.size() * 8));
     HIPCHK(put(lay.off_sigs, p.sigs.data(), p.sigs.size() * 8));
@@ -2152,13 +2188,14 @@ void Solver::choose_lane_window() {
 }
 
 int Solver::set_chain(int on) {
+    if (chain_only && !on) return MOC_EINVAL;
     if (on) {
         // vacuum top and bottom (every line ends on a z face), and the
         // per-lane FP32 sweep (one group chunk)
         if (n_trav == 0 || group_chunks(info.n_groups) != 1 || lane_win < 1 || (P % 2) != 0)
             return MOC_EINVAL;
     }
-    chain = on ? 1 : 0;
+    chain = on;
     drop_step_graphs();
     return MOC_OK;
 }
@@ -2192,10 +2229,13 @@ void Solver::launch_sweep(SweepArgs a, bool fp64, const int *units, int n_units,
     const bool lane = !fp64 && a.mode == 0 && a.exp_mode == 0 && walk == 1 && lane_win >= 1;
     if (lane) sw = lane_win;
     if (!units && chain && lane_path(a, fp64)) {
-        // chain-line sweep: one boundary buffer, read after its writer
+        // chain-line sweep: per-workgroup carry buffers, no boundary buffer
         WinArgs wa = lane_args(a);
-        wa.s.psi_out = wa.s.psi_in;
-        wa.chain_classes = P / 2;
+        wa.s.psi_in = nullptr;
+        wa.s.psi_out = nullptr;
+        wa.chain_classes = chain == 2 ? P : P / 2;
+        wa.chain_cap = chain_cap;
+        wa.chain_carry = ws + lay.off_ch_carry;
         wa.chain_first = ws_ptr<int>(ws, lay.off_ch_first);
         wa.chain_code = ws_ptr<int>(ws, lay.off_ch_code);
         wa.chain_pass = ws_ptr<int>(ws, lay.off_ch_pass);
@@ -2473,9 +2513,16 @@ int window_fit(const Plan &p, bool fp64) {
 int Solver::init(const Plan &p, char *workspace, size_t ws_bytes, hipStream_t st) {
     info = p.info();
     lay = make_layout(p, ws_bytes >= info.workspace_bytes_fp64);
+    chain_only = false;
     if (ws_bytes < lay.total) {
-        set_error("workspace smaller than moc_plan_info.workspace_bytes");
-        return MOC_ENOMEM;
+        // chain-only: everything but the boundary buffers, which come last
+        if (info.workspace_bytes_chain > 0 && ws_bytes >= info.workspace_bytes_chain) {
+            chain_only = true;
+        } else {
+            set_error("workspace smaller than moc_plan_info.workspace_bytes (and than "
+                      "workspace_bytes_chain)");
+            return MOC_ENOMEM;
+        }
     }
     if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) {
         set_error("workspace must be 256-byte aligned");
@@ -2493,6 +2540,12 @@ int Solver::init(const Plan &p, char *workspace, size_t ws_bytes, hipStream_t st
     if (!rc) rc = fill_zero(ws + lay.off_q, (size_t)p.n_fsr * p.G * 8, stream);
     if (!rc) rc = compute_volumes();
     if (!rc) rc = reset();
+    if (!rc && chain_only) {
+        chain_only = false;
+        rc = set_chain(2);
+        chain_only = true;
+        if (rc) set_error("a chain-only workspace needs the per-lane FP32 sweep (at most 8 groups)");
+    }
     return rc;
 }
 
@@ -2534,7 +2587,7 @@ int launch_batch_step(const BatchStep &b, hipStream_t st) {
 
 int Solver::reset() {
     int rc = fill_zero(ws + lay.off_phi, (size_t)info.n_fsr * info.n_groups * 8, stream);
-    if (!rc) rc = fill_zero(ws + lay.off_psi0, lay.psi_bytes, stream);
+    if (!rc && !chain_only) rc = fill_zero(ws + lay.off_psi0, lay.psi_bytes, stream);
     iter = 0;
     sweep_ms.clear();
     return rc;
@@ -2542,7 +2595,10 @@ int Solver::reset() {
 
 int Solver::iterate(int nit, const moc_solve_opts &o, bool time_sweep) {
     // the chain-line sweep runs only in the per-lane FP32 transport sweep
-    if (chain && !lane_path(sweep_args(o.sweep_fp64, o.exp_mode), o.sweep_fp64 != 0)) return MOC_EINVAL;
+    if (chain && !lane_path(sweep_args(o.sweep_fp64, o.exp_mode), o.sweep_fp64 != 0)) {
+        set_error("chain mode runs the per-lane FP32 sweep only (no FP64 sweep, no naive exponential)");
+        return MOC_EINVAL;
+    }
     const FsrArgs f = fsr_args();
     const long long nfg = f.n;
     const unsigned fblocks = (unsigned)((nfg + 255) / 256);
@@ -2588,7 +2644,10 @@ void Solver::drop_step_graphs() {
 
 int Solver::solve_step(const moc_solve_opts &o, double *res) {
     // the chain-line sweep runs only in the per-lane FP32 transport sweep
-    if (chain && !lane_path(sweep_args(o.sweep_fp64, o.exp_mode), o.sweep_fp64 != 0)) return MOC_EINVAL;
+    if (chain && !lane_path(sweep_args(o.sweep_fp64, o.exp_mode), o.sweep_fp64 != 0)) {
+        set_error("chain mode runs the per-lane FP32 sweep only (no FP64 sweep, no naive exponential)");
+        return MOC_EINVAL;
+    }
     const int key = (o.sweep_fp64 ? 1 : 0) | (o.exp_mode ? 2 : 0) | (walk << 2);
     if (!h_res) HIPCHK(hipHostMalloc((void **)&h_res, 64, hipHostMallocDefault));
     for (int b = 0; b < 2; ++b)
@@ -2707,7 +2766,10 @@ int Solver::read_stats(moc_stats *st) {
 int Solver::solve_eigen(const double *nusf, const double *chi, const moc_solve_opts &o, double *k_out,
                         double *res_out, int *iters_out) {
     // the chain-line sweep runs only in the per-lane FP32 transport sweep
-    if (chain && !lane_path(sweep_args(o.sweep_fp64, o.exp_mode), o.sweep_fp64 != 0)) return MOC_EINVAL;
+    if (chain && !lane_path(sweep_args(o.sweep_fp64, o.exp_mode), o.sweep_fp64 != 0)) {
+        set_error("chain mode runs the per-lane FP32 sweep only (no FP64 sweep, no naive exponential)");
+        return MOC_EINVAL;
+    }
     const int G = info.n_groups;
     const size_t mg = (size_t)n_materials * G;
     double *d_nusf = ws_ptr<double>(ws, lay.off_nusf), *d_chi = ws_ptr<double>(ws, lay.off_chi);
@@ -2782,6 +2844,10 @@ int Solver::read_residual(double *r) {
 
 int Solver::sweep_items(long long n_items, const long long *items, const double *qhat,
                         const double *psi_in, int fp64, double *acc_out, double *psi_out) {
+    if (chain_only) {
+        set_error("a chain-only solver has no boundary buffer for the test hooks");
+        return MOC_EINVAL;
+    }
     const int G = info.n_groups, T = info.tracks_per_wave;
     const long long nfg = (long long)info.n_fsr * G;
     // staging inside the workspace: items, entry and exit flux per (item, lane)
@@ -2854,6 +2920,10 @@ int Solver::sweep_items(long long n_items, const long long *items, const double 
 }
 
 int Solver::gather_boundary(long long n, const long long *slots, double *out) {
+    if (chain_only) {
+        set_error("a chain-only solver has no boundary buffers");
+        return MOC_EINVAL;
+    }
     if (n <= 0) return MOC_OK;
     const int G = info.n_groups;
     // the buffer the next iteration reads: psi0 after an even number of iterations

@@ -49,7 +49,8 @@ class PlanInfo(C.Structure):
                 ("n_stacks", C.c_longlong), ("n_3d_tracks", C.c_longlong),
                 ("n_chunks", C.c_longlong), ("n_groups", C.c_int), ("tracks_per_wave", C.c_int),
                 ("dz", C.c_double), ("workspace_bytes", C.c_size_t), ("psi_bytes", C.c_size_t),
-                ("workspace_bytes_fp64", C.c_size_t), ("line_stride", C.c_int)]
+                ("workspace_bytes_fp64", C.c_size_t), ("line_stride", C.c_int),
+                ("workspace_bytes_chain", C.c_size_t)]
 
 
 class StoreInfo(C.Structure):
@@ -229,13 +230,19 @@ class Solver:
     the default stream)."""
 
     def __init__(self, plan: Plan, device="cuda", workspace=None, fp64_boundary=None, walk="auto",
-                 stream="own"):
+                 stream="own", chain_only=False):
         import torch
         self.plan = plan
         self.info = plan.info
-        if fp64_boundary is None:   # FP64 boundary flux when it costs < 1 GiB
-            fp64_boundary = plan.info["workspace_bytes_fp64"] < (1 << 30)
-        nbytes = int(plan.info["workspace_bytes_fp64" if fp64_boundary else "workspace_bytes"])
+        if chain_only:
+            # no boundary buffers: the solver sweeps chain lines only
+            if not plan.info["workspace_bytes_chain"]:
+                raise MocError(MOC_EINVAL, "the plan has no chain-line sweep (vacuum top and bottom)")
+            nbytes = int(plan.info["workspace_bytes_chain"])
+        else:
+            if fp64_boundary is None:   # FP64 boundary flux when it costs < 1 GiB
+                fp64_boundary = plan.info["workspace_bytes_fp64"] < (1 << 30)
+            nbytes = int(plan.info["workspace_bytes_fp64" if fp64_boundary else "workspace_bytes"])
         if workspace is None:
             workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
         self.workspace = workspace
@@ -363,8 +370,10 @@ class Solver:
     def set_chain(self, on=True):
         """Chain-line sweeping (moc_solver_set_chain): every line swept whole
         from the z face it enters through to the one it leaves through, the
-        flux crossing reflective side faces within the sweep."""
-        _check(lib().moc_solver_set_chain(self._h, 1 if on else 0))
+        flux crossing reflective side faces within the sweep.  on: False/0,
+        True/1 (a workgroup per directed cycle and polar angle) or 2 (rising
+        and falling lines in workgroups of their own)."""
+        _check(lib().moc_solver_set_chain(self._h, int(on)))
 
     def set_window(self, threads=0):
         """Workgroup size of the per-lane sweep: 0 (automatic), 256, 512, 1024."""

@@ -22,6 +22,9 @@
   python -m paper_2503_17743_amd.study chain [--workload lattice8] [--iters 5] [--tol 1e-6]
       Lagged against chain-line sweeping: median sweep time of each, and (with
       --tol > 0) the iterations and time each takes to converge.
+  python -m paper_2503_17743_amd.study chain_only [--workload lattice64] [--iters 10]
+      A chain-only solver (no boundary buffers): workspace size, sweep time
+      and residual history.
 
 Progress goes to stderr.
 """
@@ -273,12 +276,12 @@ def chain_study(name, iters=5, tol=1e-6, max_iters=2000, sizes=(0,)):
     s.set_source(prob.q)
     for nt in sizes:
         s.set_window(nt)
-        for chain in (False, True):
+        for chain in (0, 1, 2):
             s.set_chain(chain)
             s.reset()
             s.iterate(1, stats=False)
             st = s.iterate(iters)
-            row = {"mode": "chain" if chain else "lagged", "threads": s.window()[0],
+            row = {"mode": ("lagged", "chain", "chain split")[chain], "threads": s.window()[0],
                    "segments_per_window": s.window()[1], "sweep_ms_median": st["sweep_ms_median"],
                    "seg_group_per_s": st["seg_group_updates"] / (st["sweep_ms_median"] * 1e-3)}
             _log(f"chain {name}: {row}")
@@ -286,18 +289,50 @@ def chain_study(name, iters=5, tol=1e-6, max_iters=2000, sizes=(0,)):
     s.set_window(0)
     if tol > 0:
         out["converge"] = []
-        for chain in (False, True):
+        for chain in (0, 2):
             s.set_chain(chain)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             phi, st = s.solve(tol=tol, max_iters=max_iters)
             torch.cuda.synchronize()
-            row = {"mode": "chain" if chain else "lagged", "iters": st["iters"],
+            row = {"mode": "chain split" if chain else "lagged", "iters": st["iters"],
                    "converged": st["converged"], "residual": st["residual"],
                    "wall_s": time.perf_counter() - t0, "sweep_ms_median": st["sweep_ms_median"]}
             _log(f"chain {name} converge: {row}")
             out["converge"].append(row)
-        s.set_chain(False)
+        s.set_chain(0)
+    s.close()
+    return out
+
+
+def chain_only_study(name, iters=10):
+    """A chain-only solver (workspace without boundary buffers): workspace
+    size against the full one, median sweep time and residual history over
+    `iters` source iterations."""
+    import torch
+    prob = P.get(name)
+    plan = moc.Plan(prob)
+    info = plan.info
+    s = moc.Solver(plan, chain_only=True)
+    s.set_source(prob.q)
+    hist, sweeps = [], []
+    t0 = time.perf_counter()
+    for k in range(iters):
+        st = s.iterate(1)
+        hist.append(st["residual"])
+        sweeps.append(st["sweep_ms_median"])
+        _log(f"chain-only {name}: iteration {k + 1}/{iters} residual {st['residual']:.3e} "
+             f"sweep {st['sweep_ms_median']:.1f} ms")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out = {"study": "chain_only", "workload": name, "iterations": iters,
+           "workspace_bytes_full": info["workspace_bytes"],
+           "workspace_bytes_chain": info["workspace_bytes_chain"],
+           "allocated_bytes": int(s.workspace.numel()), "wall_s": wall,
+           "sweep_ms_median": float(np.median(sweeps)),
+           "seg_group_per_s": st["seg_group_updates"] / (float(np.median(sweeps)) * 1e-3),
+           "residual_history": hist, "seg_group_updates_per_sweep": st["seg_group_updates"],
+           "link_errors": st["link_errors"], "window": s.window()}
     s.close()
     return out
 
@@ -305,7 +340,8 @@ def chain_study(name, iters=5, tol=1e-6, max_iters=2000, sizes=(0,)):
 def main(argv=None):
     import torch
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=("precision", "scale", "eigen", "exp", "window", "bundles", "chain"))
+    ap.add_argument("study", choices=("precision", "scale", "eigen", "exp", "window", "bundles", "chain",
+                                     "chain_only"))
     ap.add_argument("--workload", default=None)
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--walk", choices=("auto", "lockstep", "lane"), default="auto")
@@ -320,6 +356,8 @@ def main(argv=None):
         out = bundles_study(args.workload or "lattice32", args.iters or 5)
     elif args.study == "exp":
         out = exp_study(args.workload or "lattice8", args.iters or 10)
+    elif args.study == "chain_only":
+        out = chain_only_study(args.workload or "lattice64", args.iters or 10)
     elif args.study == "chain":
         out = chain_study(args.workload or "lattice8", args.iters or 5, tol=args.tol)
     elif args.study == "eigen":

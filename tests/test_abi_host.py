@@ -51,6 +51,17 @@ def test_library_shares_torchs_hip_runtime():
     assert r.returncode == 0, r.stderr[-2000:]
 
 
+def test_chain_only_workspace_size():
+    """A chain-only solver's workspace is the full one without the two
+    boundary buffers (which the layout puts last); plans without vacuum top
+    and bottom faces have none."""
+    for prob in (P.small_lattice(), P.get("lattice8")):
+        info = moc.Plan(prob).info
+        assert info["workspace_bytes_chain"] == info["workspace_bytes"] - info["psi_bytes"]
+        assert info["psi_bytes"] >= 2 * 2 * info["n_3d_tracks"] * prob.n_groups * 4
+    assert moc.Plan(P.config_plain()).info["workspace_bytes_chain"] == 0
+
+
 def _plan_err(prob):
     with pytest.raises(moc.MocError) as e:
         moc.Plan(prob)

@@ -159,6 +159,51 @@ def test_chain_window_sizes_agree(moc):
     assert ref is not None
 
 
+def test_chain_split_matches_oracle(moc, nthreads):
+    """Rising and falling lines in workgroups of their own (on = 2): the same
+    iterates as the oracle's chain mode."""
+    prob = P.small_lattice()
+    plan = moc.Plan(prob)
+    s = moc.Solver(plan)
+    s.set_source(prob.q)
+    s.set_chain(2)
+    st = s.iterate(3)
+    om = O.Model(prob, n_threads=nthreads)
+    ophi, ores = om.solve(tol=0.0, max_iters=3, chain=True)
+    assert _relerr(s.flux(), ophi) < TOL32
+    assert st["seg_group_updates"] == 2 * om.info["n_segments"] * prob.n_groups
+    assert st["link_errors"] == 0
+
+
+def test_chain_only_solver(moc, nthreads):
+    """A workspace without the boundary buffers gives a chain-only solver
+    (split classes): the oracle's chain iterates, the full solver's results,
+    and no way out of chain mode or into the hooks that need the buffers."""
+    prob = P.small_lattice()
+    plan = moc.Plan(prob)
+    s = moc.Solver(plan, chain_only=True)
+    assert s.workspace.numel() < plan.info["workspace_bytes"]
+    s.set_source(prob.q)
+    st = s.iterate(3)
+    om = O.Model(prob, n_threads=nthreads)
+    ophi, _ = om.solve(tol=0.0, max_iters=3, chain=True)
+    assert _relerr(s.flux(), ophi) < TOL32
+    assert st["seg_group_updates"] == 2 * om.info["n_segments"] * prob.n_groups
+    full = moc.Solver(plan)
+    full.set_source(prob.q)
+    full.set_chain(2)
+    full.iterate(3)
+    assert _relerr(s.flux(), full.flux()) < 1e-6
+    with pytest.raises(moc.MocError):
+        s.set_chain(False)
+    with pytest.raises(moc.MocError):
+        s.boundary_flux(np.zeros(1, np.int64))
+    # moc_solve (captured iterations) in the chain-only solver
+    phi, stc = s.solve(tol=1e-6, max_iters=500)
+    oconv, _ = om.solve(tol=1e-11, max_iters=500, chain=True)
+    assert stc["converged"] and _relerr(phi, oconv) < TOL32
+
+
 def test_chain_rejections(moc):
     """Chain mode needs vacuum top and bottom faces, and in chain mode the
     FP64 sweep is refused rather than run lagged."""
