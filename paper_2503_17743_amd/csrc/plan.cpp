@@ -539,6 +539,29 @@ std::string Plan::build(const moc_geometry &g, const moc_tracking &t, const moc_
         int64_t covered = 0;
         for (int64_t i = 0; i < (int64_t)ch_code.size(); ++i) covered += ch_pass[i] == 0;
         if (covered != 2 * n2d) return "internal: traversals do not cover every unit";
+        // longest traversals first: workgroups start in index order, and a
+        // long traversal started last would set the sweep's length
+        std::vector<int64_t> ord(n_trav);
+        std::iota(ord.begin(), ord.end(), 0);
+        std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) {
+            return ch_first[x + 1] - ch_first[x] > ch_first[y + 1] - ch_first[y];
+        });
+        std::vector<int> f2(1, 0), c2, p2;
+        std::vector<double> s2, l2;
+        for (int64_t k : ord) {
+            for (int i = ch_first[k]; i < ch_first[k + 1]; ++i) {
+                c2.push_back(ch_code[i]);
+                p2.push_back(ch_pass[i]);
+                s2.push_back(ch_spos[i]);
+            }
+            l2.push_back(ch_lc[k]);
+            f2.push_back((int)c2.size());
+        }
+        ch_first.swap(f2);
+        ch_code.swap(c2);
+        ch_pass.swap(p2);
+        ch_spos.swap(s2);
+        ch_lc.swap(l2);
         ch_cap = 0;
         for (int64_t s = 0; s < n_stacks; ++s) ch_cap = std::max(ch_cap, cnt[s]);
     }
