@@ -265,6 +265,40 @@ def small_workload(name, steps, oracle_iters, cpu_leg):
     }
 
 
+def chain_leg(name, iters, cpu_leg):
+    """Chain-line sweeping on a small workload: a chain-only solver (no
+    boundary buffers) against the full lagged one, its sweep time, and its
+    iterate after `iters` iterations against the oracle's chain iterate."""
+    import numpy as np
+    from paper_2503_17743_amd import moc, problems as P
+    prob = P.get(name)
+    plan = moc.Plan(prob)
+    solver = moc.Solver(plan, chain_only=True)
+    solver.set_source(prob.q)
+    log(f"{name}: {iters} chain-line iterations ...")
+    st = solver.iterate(iters)
+    gphi = solver.flux()
+    window = solver.window()
+    solver.close()
+    parity = None
+    if cpu_leg:
+        from oracle import oracle as O
+        m = O.Model(prob, n_threads=oracle_threads())
+        ophi, _ = m.solve(max_iters=iters, tol=0.0, chain=True)
+        parity = float(np.max(np.abs(gphi - ophi) / np.maximum(np.abs(ophi), 1e-300)))
+    return {
+        "workload": name,
+        "iterations": iters,
+        "sweep_ms_median": st["sweep_ms_median"],
+        "seg_group_per_s": st["seg_group_updates"] / (st["sweep_ms_median"] * 1e-3),
+        "workspace_bytes_chain_only": plan.info["workspace_bytes_chain"],
+        "workspace_bytes_lagged": plan.info["workspace_bytes"],
+        "link_errors": st["link_errors"],
+        "threads": window[0],
+        "max_rel_err_vs_fp64_oracle_chain": parity,
+    }
+
+
 def roofline(segg, sweep_s, counters):
     """The sweep's binding roof: vector ALU issue (measured wave64 VALU issue
     slots per launch, SQ_ACTIVE_INST_VALU, in which a transcendental counts
@@ -303,6 +337,9 @@ def main():
     ap.add_argument("--sample-tracks", type=int, default=400000,
                     help="directed tracks of the sampled oracle sweep on the headline workload")
     ap.add_argument("--walk", choices=("auto", "lockstep", "lane"), default="auto")
+    ap.add_argument("--chain-workload", default="lattice8",
+                    help="a small problem also swept in chain-line mode ('' to skip)")
+    ap.add_argument("--chain-iters", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=32,
                     help="requests in the serving comparison (0: skip it)")
@@ -332,6 +369,9 @@ def main():
     if args.small_workload:
         small = small_workload(args.small_workload, args.small_steps, args.oracle_iters,
                                not args.no_cpu_baseline)
+    chain = None
+    if args.chain_workload:
+        chain = chain_leg(args.chain_workload, args.chain_iters, not args.no_cpu_baseline)
     serving = None
     if args.serving_requests > 0:
         serving = S.compare(args.serving_requests, args.serving_arena_gib, log=log)
@@ -391,6 +431,7 @@ def main():
             "walk": solver_walk,
             "sampled_oracle_parity": parity,
             "small_workload": small,
+            "chain_line": chain,
         },
         "roofline": roofline(segg, sweep_s, load_counters(prob.name)),
         "cpu_baseline": cpu,

@@ -204,6 +204,26 @@ def test_chain_only_solver(moc, nthreads):
     assert stc["converged"] and _relerr(phi, oconv) < TOL32
 
 
+def test_chain_eigenvalue_matches_oracle(moc, nthreads):
+    """Power iteration on k-eff with chain-line sweeps (chain-only solver) has
+    the lagged iteration's fixed point: k and the flux shape within 1e-5 of
+    the oracle's converged FP64 solution."""
+    p = P.small_lattice()
+    nsf, chi = P.fission_data(p)
+    s = moc.Solver(moc.Plan(p), chain_only=True)
+    s.set_source(p.q)
+    _, _, st6 = s.solve_eigen(nsf, chi, tol=1e-6, max_iters=2000)
+    assert st6["converged"]
+    phi, k, st = s.solve_eigen(nsf, chi, tol=0.0, max_iters=600)
+    om = O.Model(p, n_threads=nthreads)
+    ophi, ok, ores = om.solve_eigen(nsf, chi, tol=1e-10, max_iters=5000)
+    print(f"chain k {k:.8f} oracle {ok:.8f}, iterations to 1e-6 {st6['iters']}")
+    assert abs(k - ok) < 1e-5 * ok
+    a, b = phi / np.sum(phi), ophi / np.sum(ophi)
+    m = b > 0
+    assert np.max(np.abs(a[m] - b[m]) / b[m]) < 1e-5
+
+
 def test_chain_rejections(moc):
     """Chain mode needs vacuum top and bottom faces, and in chain mode the
     FP64 sweep is refused rather than run lagged."""
