@@ -116,6 +116,7 @@ typedef struct {
     size_t workspace_bytes_chain; /* bytes for a chain-only solver: no boundary    */
                                   /* buffers (moc_solver_set_chain; 0: the plan has */
                                   /* no vacuum top and bottom faces)                */
+    long long n_chain_segments;   /* independent jobs of a chain-line sweep        */
 } moc_plan_info;
 
 /* Solve controls.  sweep_fp64 = 1 runs segment arithmetic and angular flux in

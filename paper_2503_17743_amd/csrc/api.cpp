@@ -214,7 +214,7 @@ int moc_solver_set_bundles(moc_solver *sv, int mode) {
 
 int moc_solver_set_chain(moc_solver *sv, int on) {
     if (!sv) return fail(MOC_EINVAL, "NULL solver");
-    if (on < 0 || on > 2) return fail(MOC_EINVAL, "on must be 0, 1 or 2");
+    if (on != 0 && on != 1) return fail(MOC_EINVAL, "on must be 0 or 1");
     if (sv->s.chain_only && on == 0) return fail(MOC_EINVAL, "a chain-only solver cannot leave chain mode");
     if (sv->s.set_chain(on))
         return fail(MOC_EINVAL, "the chain-line sweep needs vacuum top and bottom faces, an even polar "

@@ -62,26 +62,23 @@ struct WinArgs {
     const unsigned *exp_tbase;       // first step-table entry of each unit of the launch
     unsigned *exp_table;             // per (unit, window, bundle): steps, then their exclusive prefix
     Piece *exp_data;                 // recorded pieces [wave step][64 lanes]
-    // chain-line sweep: workgroup b sweeps traversal b / chain_classes, the
-    // stacks of polar class b mod chain_classes (P / 2 classes: the |cot|
-    // index, stacks n and P - 1 - n; P classes: each of those split into its
-    // rising and falling lines), item by item (see Plan::ch_*)
-    int chain_classes;
-    int chain_cap;                    // lines of the largest stack
-    const int *chain_first, *chain_code, *chain_pass;
-    const double *chain_spos, *chain_lc;
-    void *chain_carry;                // per workgroup: [2 parities][2 stacks][chain_cap][G] fluxes
+    // chain-line sweep: each workgroup takes segments (chain_ctr, a counter
+    // from zero) and sweeps their items in order (see Plan::ch_*)
+    int chain_nseg, chain_cap;
+    const int *chain_first, *chain_code, *chain_k, *chain_nk;
+    const double *chain_u, *chain_lc;
+    unsigned *chain_ctr;
+    void *chain_carry;                // per workgroup: [2 parities][P stacks][chain_cap][G] fluxes
 };
 
-// The lines of one chain-sweep item: polar class, pass, the unit's unrolled
-// start along its traversal and the traversal's length.
+// The lines of one chain-sweep item: segment k of nk of a traversal of
+// length lc, the unit's unrolled start u, and the workgroup's carries.
 struct ChainItem {
-    int cls, pass;
-    bool split;     // classes split into rising and falling lines
+    int seg, nseg;
     int par;        // carry buffer of this item (the next item's is par ^ 1)
     int cap;        // lines per stack in a carry buffer
     void *carry;    // this workgroup's carry buffers
-    double spos, lc;
+    double u, lc;
 };
 
 // Per-problem control of a batched step: the stopping rule and the state the

@@ -484,85 +484,113 @@ std::string Plan::build(const moc_geometry &g, const moc_tracking &t, const moc_
     // to the other, so a sweep can follow it whole.  Each directed cycle is
     // walked from its chain origin (the start of the track C runs forward
     // from chain position 0), where every line of every stack sits at
-    // z = (i + 1/2) dz: the pass boundaries (a line's 2D distance from its
-    // entry face to the origin, a multiple of the cycle length) then fall
-    // half a spacing away from every line.  A line rising by at most H over
-    // a 2D distance of H / min|cot| reaches past the origin into pass p only
-    // at units starting before H / min|cot| - (p - 1) L_C.
+    // z = (i + 1/2) dz: lines then enter through a z face half an entry
+    // spacing away from every segment bound (whole spacings from the origin).
+    // A line rises by H over a 2D distance of H / |cot| (its reach), so the
+    // lines of a segment [A, B) cross only the units in [A, B + reach).
     n_trav = 0;
+    n_chseg = 0;
     ch_first.assign(1, 0);
     ch_code.clear();
-    ch_pass.clear();
-    ch_spos.clear();
+    ch_u.clear();
+    ch_k.clear();
+    ch_nk.clear();
     ch_lc.clear();
+    ch_cap = 0;
     if (bc[MOC_FACE_ZMIN] == MOC_BC_VACUUM && bc[MOC_FACE_ZMAX] == MOC_BC_VACUUM) {
-        std::vector<int64_t> units;
-        std::vector<double> spos;
+        struct Trav {
+            std::vector<int64_t> units;
+            std::vector<double> spos;
+            double lc;
+            int az;
+        };
+        std::vector<Trav> travs;
         for (int64_t t0 = 0; t0 < n2d; ++t0) {
             if (!(sig[t0] == 1 && chain[t0] == 0.0)) continue;
-            double cmin = 0.0;
-            for (int n = 0; n < P; ++n) {
-                const double c = std::fabs(cot[az[t0] * P + n]);
-                if (n == 0 || c < cmin) cmin = c;
-            }
             for (int rev = 0; rev < 2; ++rev) {
+                Trav tv;
+                tv.az = az[t0];
                 const int64_t start = rev ? link[2 * t0 + 1] : 2 * t0;
-                units.clear();
-                spos.clear();
                 double pos = 0.0;
                 int64_t u = start;
                 do {
-                    units.push_back(u);
-                    spos.push_back(pos);
+                    tv.units.push_back(u);
+                    tv.spos.push_back(pos);
                     pos += L[u / 2];
                     u = link[u];
-                    if ((int64_t)units.size() > 2 * n2d) return "internal: traversal does not close";
+                    if ((int64_t)tv.units.size() > 2 * n2d) return "internal: traversal does not close";
                 } while (u != start);
-                const double lc = pos, reach = H / cmin;
-                for (int pass = 0;; ++pass) {
-                    const double lim = reach - (pass - 1) * lc;
-                    size_t added = 0;
-                    for (size_t j = 0; j < units.size(); ++j)
-                        if (pass == 0 || spos[j] < lim) {
-                            ch_code.push_back((int)units[j]);
-                            ch_pass.push_back(pass);
-                            ch_spos.push_back(spos[j]);
-                            ++added;
-                        }
-                    if (added == 0) break;
-                }
-                ch_lc.push_back(lc);
-                ch_first.push_back((int)ch_code.size());
-                ++n_trav;
+                tv.lc = pos;
+                travs.push_back(std::move(tv));
             }
         }
+        n_trav = (int64_t)travs.size();
         int64_t covered = 0;
-        for (int64_t i = 0; i < (int64_t)ch_code.size(); ++i) covered += ch_pass[i] == 0;
-        if (covered != 2 * n2d) return "internal: traversals do not cover every unit";
-        // longest traversals first: workgroups start in index order, and a
-        // long traversal started last would set the sweep's length
-        std::vector<int64_t> ord(n_trav);
-        std::iota(ord.begin(), ord.end(), 0);
-        std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) {
-            return ch_first[x + 1] - ch_first[x] > ch_first[y + 1] - ch_first[y];
-        });
-        std::vector<int> f2(1, 0), c2, p2;
-        std::vector<double> s2, l2;
-        for (int64_t k : ord) {
-            for (int i = ch_first[k]; i < ch_first[k + 1]; ++i) {
-                c2.push_back(ch_code[i]);
-                p2.push_back(ch_pass[i]);
-                s2.push_back(ch_spos[i]);
-            }
-            l2.push_back(ch_lc[k]);
-            f2.push_back((int)c2.size());
+        double total = 0.0, reach_max = 0.0;
+        for (const Trav &tv : travs) {
+            covered += (int64_t)tv.units.size();
+            total += tv.lc;
+            for (int n = P / 2; n < P; ++n) reach_max = std::max(reach_max, H / cot[tv.az * P + n]);
         }
-        ch_first.swap(f2);
-        ch_code.swap(c2);
-        ch_pass.swap(p2);
-        ch_spos.swap(s2);
-        ch_lc.swap(l2);
-        ch_cap = 0;
+        if (covered != 2 * n2d) return "internal: traversals do not cover every unit";
+        // segments of about the same length: at least four reaches long (a
+        // segment's units past its end carry only its last lines), and small
+        // enough that a few thousand of them share out the sweep
+        const double lseg = std::max(4.0 * reach_max, total / 2048.0);
+        struct Seg {
+            int k, nk;
+            double lc;
+            std::vector<int> code;
+            std::vector<double> u;
+        };
+        std::vector<Seg> segs;
+        for (const Trav &tv : travs) {
+            const int nk = (int)std::max(1.0, std::floor(tv.lc / lseg));
+            const int m = (int)tv.units.size();
+            for (int k = 0; k < nk; ++k) {
+                double lo = 1e300, hi = -1e300;
+                for (int n = P / 2; n < P; ++n) {
+                    const double c = cot[tv.az * P + n];
+                    const int64_t kk = std::llround(tv.lc * c / dz);
+                    const double sp = tv.lc / (double)kk;
+                    const double a0 = (double)((int64_t)k * kk / nk) * sp;
+                    const double a1 = (double)((int64_t)(k + 1) * kk / nk) * sp;
+                    lo = std::min(lo, a0);
+                    hi = std::max(hi, a1 + H / c);
+                }
+                Seg sg;
+                sg.k = k;
+                sg.nk = nk;
+                sg.lc = tv.lc;
+                // from the unit holding lo, in traversal order, until past hi
+                int j = (int)(std::upper_bound(tv.spos.begin(), tv.spos.end(), lo) - tv.spos.begin()) - 1;
+                j = std::max(j, 0);
+                double lap = 0.0;
+                for (;;) {
+                    const double u = tv.spos[j] + lap;
+                    if (u >= hi) break;
+                    sg.code.push_back((int)tv.units[j]);
+                    sg.u.push_back(u);
+                    if (++j == m) {
+                        j = 0;
+                        lap += tv.lc;
+                    }
+                }
+                segs.push_back(std::move(sg));
+            }
+        }
+        // longest first: workgroups take the next segment as they finish
+        std::stable_sort(segs.begin(), segs.end(),
+                         [](const Seg &x, const Seg &y) { return x.code.size() > y.code.size(); });
+        for (const Seg &sg : segs) {
+            ch_code.insert(ch_code.end(), sg.code.begin(), sg.code.end());
+            ch_u.insert(ch_u.end(), sg.u.begin(), sg.u.end());
+            ch_first.push_back((int)ch_code.size());
+            ch_k.push_back(sg.k);
+            ch_nk.push_back(sg.nk);
+            ch_lc.push_back(sg.lc);
+        }
+        n_chseg = (int64_t)segs.size();
         for (int64_t s = 0; s < n_stacks; ++s) ch_cap = std::max(ch_cap, cnt[s]);
     }
     return "";
@@ -586,7 +614,8 @@ moc_plan_info Plan::info() const {
     o.workspace_bytes = l.total;
     o.psi_bytes = l.psi_bytes;
     o.workspace_bytes_fp64 = make_layout(*this, true).total;
-    o.workspace_bytes_chain = n_trav > 0 ? l.off_psi0 : 0;
+    o.workspace_bytes_chain = n_chseg > 0 ? l.off_psi0 : 0;
+    o.n_chain_segments = n_chseg;
     return o;
 }
 
@@ -629,12 +658,15 @@ Layout make_layout(const Plan &p, bool psi64) {
     l.off_phi = take(nfg * 8);
     l.off_vol = take((size_t)p.n_fsr * 8);
     l.off_work = take((size_t)2 * p.n2d * 4);
-    l.off_ch_first = take((p.n_trav + 1) * 4);
+    l.off_ch_first = take((p.n_chseg + 1) * 4);
     l.off_ch_code = take(p.ch_code.size() * 4 + 4);
-    l.off_ch_pass = take(p.ch_pass.size() * 4 + 4);
-    l.off_ch_spos = take(p.ch_spos.size() * 8 + 8);
-    l.off_ch_lc = take(p.n_trav * 8 + 8);
-    l.off_ch_carry = take((size_t)p.n_trav * p.P * 4 * (size_t)p.ch_cap * p.G * (psi64 ? 8 : 4));
+    l.off_ch_u = take(p.ch_u.size() * 8 + 8);
+    l.off_ch_k = take(p.n_chseg * 4 + 4);
+    l.off_ch_nk = take(p.n_chseg * 4 + 4);
+    l.off_ch_lc = take(p.n_chseg * 8 + 8);
+    l.off_ch_ctr = take(4);
+    const size_t slots = p.n_chseg > 0 ? (size_t)std::min<int64_t>(p.n_chseg, kChainSlots) : 0;
+    l.off_ch_carry = take(slots * 2 * p.P * (size_t)p.ch_cap * p.G * (psi64 ? 8 : 4));
     l.off_scal = take(128 * 1024);
     l.off_nusf = take((size_t)p.M * p.G * 8);
     l.off_chi = take((size_t)p.M * p.G * 8);

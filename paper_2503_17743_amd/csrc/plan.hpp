@@ -30,6 +30,8 @@ inline int groups_per_lane(int G) { return (G + group_chunks(G) - 1) / group_chu
 // Per-item stride (doubles) of the test hooks' entry/exit flux buffers: T * G
 // never exceeds 64 * kGL.
 constexpr int kItemStride = 64 * kGL;
+// Workgroups of a chain-line sweep (each holds its own carry buffers)
+constexpr int kChainSlots = 512;
 
 struct Plan {
     // ---- problem ----
@@ -68,15 +70,20 @@ struct Plan {
 
     // ---- chain-line sweep (vacuum top and bottom faces only) ----
     // A traversal is a directed 2D cycle, its units (2*t + dir) in link order
-    // from the cycle's chain origin.  Its items are the units of pass 0, then
-    // of the later passes those that lines wrapping past the origin reach:
-    // unit code, pass and the unit's start as unrolled 2D position along the
-    // traversal; ch_lc is each traversal's length.
-    int64_t n_trav = 0;
-    std::vector<int> ch_first;                 // [n_trav+1] item range of each traversal
-    std::vector<int> ch_code, ch_pass;         // [items]
-    std::vector<double> ch_spos;               // [items]
-    std::vector<double> ch_lc;                 // [n_trav]
+    // from the cycle's chain origin.  Each traversal is cut into segments:
+    // segment k of K takes, for every polar angle, the lines entering the box
+    // (rising through the bottom face, falling through the top one) within
+    // [A_k, A_{k+1}) of the traversal's length, A_k a whole number of that
+    // angle's entry spacings L_C / kk (kk lines cross a point per cycle).  Its
+    // items are the units those lines cross, in traversal order, with each
+    // unit's unrolled start (its start plus whole traversal lengths once the
+    // lines wrap past the origin).  Segments are listed longest first.
+    int64_t n_trav = 0, n_chseg = 0;
+    std::vector<int> ch_first;                 // [n_chseg+1] item range of each segment
+    std::vector<int> ch_code;                  // [items] unit code
+    std::vector<double> ch_u;                  // [items] unrolled start of the unit
+    std::vector<int> ch_k, ch_nk;              // [n_chseg] segment index, segments of its traversal
+    std::vector<double> ch_lc;                 // [n_chseg] length of its traversal
     int64_t ch_cap = 0;                        // lines of the largest stack
 
     std::string build(const moc_geometry &g, const moc_tracking &t, const moc_xs &x);
@@ -104,9 +111,10 @@ struct Layout {
     size_t off_units = 0, off_filt_n = 0, off_filt_i0 = 0;
     size_t n_item_cap = 0, scratch_bytes = 0;
     size_t off_work = 0;            // windowed-sweep work list (2 * n2d codes)
-    size_t off_ch_first = 0, off_ch_code = 0, off_ch_pass = 0, off_ch_spos = 0, off_ch_lc = 0;
-    // chain sweep carry buffers: per workgroup (n_trav * P at most) two
-    // parities x two stacks x ch_cap lines x G fluxes of the boundary type
+    size_t off_ch_first = 0, off_ch_code = 0, off_ch_u = 0, off_ch_k = 0, off_ch_nk = 0, off_ch_lc = 0;
+    size_t off_ch_ctr = 0;          // next segment to take (reset before each chain sweep)
+    // chain sweep carry buffers: per workgroup (kChainSlots at most) two
+    // parities x P stacks x ch_cap lines x G fluxes of the boundary type
     size_t off_ch_carry = 0;
     bool psi64 = false;             // boundary angular flux stored in FP64
 };

@@ -103,10 +103,9 @@ struct Solver {
     bool dyn_bundles() const;
     // chain-line sweep: the flux leaving a line through a reflective side
     // face enters its continuation within the same sweep (vacuum top and
-    // bottom faces; the per-lane FP32 sweep only).  0 off; 1 one workgroup
-    // per directed cycle and |cot|; 2 per directed cycle, |cot| and z sense
+    // bottom faces; the per-lane FP32 sweep only).  0 off, 1 on
     int chain = 0;
-    int64_t n_trav = 0;
+    int64_t n_chseg = 0;
     int chain_cap = 0;               // lines per stack of a carry buffer
     bool chain_only = false;         // workspace without boundary buffers
     int set_chain(int on);

@@ -599,28 +599,28 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
         }
     };
     const int n_srch = lane;
-    // chain sweep: only the stacks of the item's polar class (|cot| index,
-    // times two with the lines rising and falling along the traversal apart:
-    // stack n rises when cot > 0, n >= P / 2, in a forward unit)
-    const bool srch = wave == 0 && n_srch < P && (fn < 0 || fn == n_srch) &&
-                      (!ci || (ci->split ? (2 * min(n_srch, P - 1 - n_srch) + ((n_srch >= P / 2) != (dir == 1))
-                                            == ci->cls)
-                                         : min(n_srch, P - 1 - n_srch) == ci->cls));
-    // Chain sweep: the lines of this stack the item's pass sweeps.  A line
-    // rising (falling) along the traversal that is at z (at H - z) where this
-    // unit starts entered through the bottom (top) face a 2D distance z / |cot|
-    // before; with x that distance minus the unit's unrolled start, pass p
-    // takes the lines with (p - 1) L_C < x <= p L_C (lines entering inside
-    // the unit have x < 0, pass 0).  The bounds fall half a spacing from
-    // every line (the traversals start where all lines sit at (i + 1/2) dz),
-    // so the closed forms need no check.
+    const bool srch = wave == 0 && n_srch < P && (fn < 0 || fn == n_srch);
+    // Chain sweep: the lines of this stack the item sweeps, those that
+    // entered the box (rising: through the bottom face, falling: the top one)
+    // within [A, B) of the traversal: segment seg of nseg, its bounds whole
+    // numbers of the stack's entry spacing lc / kk (kk lines cross a point per
+    // cycle).  A line at z (at H - z when falling) where this unit starts
+    // entered a 2D distance z / |cot| earlier, at the unrolled position
+    // u - z / |cot|.  The bounds fall half a spacing from every entry point
+    // (the traversals start where all lines sit at (i + 1/2) dz), so the
+    // closed forms need no check.
     int ch_lo = 0, ch_hi = 0x7fffffff;
     if (ci && srch) {
         const long long s = t * P + n_srch;
         const double c = a.cot[az * P + n_srch];
         const double ce = dir ? -c : c;
         const double z0 = a.zeta[s] + (double)a.ilo[s] * a.dz + c * (dir ? Lt : 0.0);
-        const double x0 = (ci->pass - 1) * ci->lc + ci->spos, x1 = ci->pass * ci->lc + ci->spos;
+        const double kk = rint(ci->lc * fabs(c) * a.inv_dz);
+        const double sp = ci->lc / kk;
+        const double ea = floor((double)ci->seg * kk / (double)ci->nseg) * sp;
+        const double eb = floor((double)(ci->seg + 1) * kk / (double)ci->nseg) * sp;
+        // entry distance d in (x0, x1]
+        const double x0 = ci->u - eb, x1 = ci->u - ea;
         const double cnt_s = (double)a.cnt[s];
         double flo, fhi;
         if (ce > 0) {
@@ -633,10 +633,6 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
         ch_lo = (int)fmin(fmax(flo, 0.0), cnt_s);
         ch_hi = (int)fmin(fmax(fhi, -1.0), cnt_s - 1.0);
     }
-    // wave 0: which lines of each polar stack cross window wi (a contiguous
-    // index range, since line extents move monotonically with the line
-    // index), and the bundle prefix over the stacks, into the line-range area
-    // (read by the bundles only, so it is rewritten during the flush)
     auto search_window = [&](const int wi) {
         int k0, nsw;
         window_of(wi, k0, nsw);
@@ -951,8 +947,8 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
             const bool ends = dir == 0 ? (le <= wb_) : (ls >= wa_);
             // the line's flux between windows (and on entry): its boundary
             // slot, or in the chain sweep its entry of the item's carry
-            // buffer (parity, stack of the class, line)
-            const long long slot = ci ? ((long long)(ci->par * 2 + (n >= P / 2)) * ci->cap + i)
+            // buffer (parity, stack, line)
+            const long long slot = ci ? ((long long)(ci->par * P + n) * ci->cap + i)
                                       : 2 * (a.trk_off[s] + i) + dir;
             B *const cbuf = ci ? (B *)ci->carry : (B *)psi_in;
             const size_t hook = (size_t)unit * kItemStride + (size_t)(i - fi0) * G + g0;
@@ -1221,7 +1217,7 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                         long long slot2 = successor_line(a, b, t, n, dir, base, c, n2, i2);
                         // chain sweep: the continuation is swept by the next
                         // item, from the other carry buffer
-                        if (ci && slot2 >= 0) slot2 = (long long)((ci->par ^ 1) * 2 + (n2 >= P / 2)) * ci->cap + i2;
+                        if (ci && slot2 >= 0) slot2 = (long long)((ci->par ^ 1) * P + n2) * ci->cap + i2;
                         if (slot2 >= 0) {
                             B *po = (ci ? (B *)ci->carry : (B *)psi_out) + slot2 * G + g0;
 #pragma unroll
@@ -1300,38 +1296,43 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     }
 }
 
-// Chain-line sweep (vacuum top and bottom faces): workgroup b follows one
-// traversal, a directed 2D cycle, for one polar class, sweeping its items in
-// order: every unit of pass 0, then the units that lines wrapping past the
-// traversal's origin reach in later passes (a later pass exists only when
-// the one before covered every unit, so a line's continuation is always in
-// the next item).  The flux a line leaves through a side face goes to its
-// continuation's entry of the workgroup's other carry buffer, which the
-// next item reads, so every line is swept whole within the sweep (no flux
-// lags an iteration) and no boundary buffer is needed.  The traversals of a
-// problem and their polar classes are independent.
+// Chain-line sweep (vacuum top and bottom faces): each workgroup takes the
+// next segment of a traversal (a directed 2D cycle) from a counter and
+// sweeps its items, the units its lines cross, in traversal order.  The
+// flux a line leaves through a side face goes to its continuation's entry
+// of the workgroup's other carry buffer, which the next item (the next unit)
+// reads, so every line is swept whole within the sweep (no flux lags an
+// iteration) and no boundary buffer is needed.  A segment's first unit holds
+// the entry points of its first lines, so no flux enters it from an earlier
+// item; the segments are independent.
 template <typename B, int GC, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_win_chain(WinArgs wa) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int tv = blockIdx.x / wa.chain_classes;
+    __shared__ int s_seg;
     ChainItem ci;
-    ci.cls = blockIdx.x - tv * wa.chain_classes;
-    ci.split = wa.chain_classes == wa.s.P;
-    ci.lc = wa.chain_lc[tv];
     ci.cap = wa.chain_cap;
-    ci.carry = (B *)wa.chain_carry + (size_t)blockIdx.x * 4 * wa.chain_cap * wa.s.G;
-    const int i0 = wa.chain_first[tv], i1 = wa.chain_first[tv + 1];
-    for (int i = i0; i < i1; ++i) {
-        const int code = wa.chain_code[i];
-        ci.pass = wa.chain_pass[i];
-        ci.spos = wa.chain_spos[i];
-        ci.par = (i - i0) & 1;
-        if (code & 1) sweep_unit<float, B, 0, 0, true, true, GC, true, NT>(wa, code, blockIdx.x, smem, false, &ci);
-        else sweep_unit<float, B, 0, 0, false, true, GC, true, NT>(wa, code, blockIdx.x, smem, false, &ci);
-        // the fluxes handed to the next units are read by any wave of this
-        // workgroup in a later item
-        __threadfence();
+    ci.carry = (B *)wa.chain_carry + (size_t)blockIdx.x * 2 * wa.s.P * wa.chain_cap * wa.s.G;
+    for (;;) {
+        if (threadIdx.x == 0) s_seg = (int)atomicAdd(wa.chain_ctr, 1u);
         __syncthreads();
+        const int sg = uniform(s_seg);
+        __syncthreads();
+        if (sg >= wa.chain_nseg) break;
+        ci.seg = wa.chain_k[sg];
+        ci.nseg = wa.chain_nk[sg];
+        ci.lc = wa.chain_lc[sg];
+        const int i0 = wa.chain_first[sg], i1 = wa.chain_first[sg + 1];
+        for (int i = i0; i < i1; ++i) {
+            const int code = wa.chain_code[i];
+            ci.u = wa.chain_u[i];
+            ci.par = (i - i0) & 1;
+            if (code & 1) sweep_unit<float, B, 0, 0, true, true, GC, true, NT>(wa, code, blockIdx.x, smem, false, &ci);
+            else sweep_unit<float, B, 0, 0, false, true, GC, true, NT>(wa, code, blockIdx.x, smem, false, &ci);
+            // the fluxes handed to the next unit are read by any wave of this
+            // workgroup in the next item
+            __threadfence();
+            __syncthreads();
+        }
     }
 }
 
@@ -1938,10 +1939,11 @@ int Solver::upload(const Plan &p) {
     HIPCHK(put(lay.off_chunk_off, p.chunk_off.data(), p.chunk_off.size() * 8));
     HIPCHK(put(lay.off_ch_first, p.ch_first.data(), p.ch_first.size() * 4));
     HIPCHK(put(lay.off_ch_code, p.ch_code.data(), p.ch_code.size() * 4));
-    HIPCHK(put(lay.off_ch_pass, p.ch_pass.data(), p.ch_pass.size() * 4));
-    HIPCHK(put(lay.off_ch_spos, p.ch_spos.data(), p.ch_spos.size() * 8));
+    HIPCHK(put(lay.off_ch_u, p.ch_u.data(), p.ch_u.size() * 8));
+    HIPCHK(put(lay.off_ch_k, p.ch_k.data(), p.ch_k.size() * 4));
+    HIPCHK(put(lay.off_ch_nk, p.ch_nk.data(), p.ch_nk.size() * 4));
     HIPCHK(put(lay.off_ch_lc, p.ch_lc.data(), p.ch_lc.size() * 8));
-    n_trav = p.n_trav;
+    n_chseg = p.n_chseg;
     chain_cap = (int)p.ch_cap;
     HIPCHK(put(lay.off_sigt32, sigt32.data(), sigt32.size() * 4));
     HIPCHK(put(lay.off_sigt64, p.sigt.data(), p.sigt.size() * 8));
@@ -2192,7 +2194,7 @@ int Solver::set_chain(int on) {
     if (on) {
         // vacuum top and bottom (every line ends on a z face), and the
         // per-lane FP32 sweep (one group chunk)
-        if (n_trav == 0 || group_chunks(info.n_groups) != 1 || lane_win < 1 || (P % 2) != 0)
+        if (n_chseg == 0 || group_chunks(info.n_groups) != 1 || lane_win < 1 || (P % 2) != 0)
             return MOC_EINVAL;
     }
     chain = on;
@@ -2233,16 +2235,21 @@ void Solver::launch_sweep(SweepArgs a, bool fp64, const int *units, int n_units,
         WinArgs wa = lane_args(a);
         wa.s.psi_in = nullptr;
         wa.s.psi_out = nullptr;
-        wa.chain_classes = chain == 2 ? P : P / 2;
+        wa.chain_nseg = (int)n_chseg;
         wa.chain_cap = chain_cap;
         wa.chain_carry = ws + lay.off_ch_carry;
         wa.chain_first = ws_ptr<int>(ws, lay.off_ch_first);
         wa.chain_code = ws_ptr<int>(ws, lay.off_ch_code);
-        wa.chain_pass = ws_ptr<int>(ws, lay.off_ch_pass);
-        wa.chain_spos = ws_ptr<double>(ws, lay.off_ch_spos);
+        wa.chain_u = ws_ptr<double>(ws, lay.off_ch_u);
+        wa.chain_k = ws_ptr<int>(ws, lay.off_ch_k);
+        wa.chain_nk = ws_ptr<int>(ws, lay.off_ch_nk);
         wa.chain_lc = ws_ptr<double>(ws, lay.off_ch_lc);
-        const unsigned nb = (unsigned)(n_trav * wa.chain_classes);
+        wa.chain_ctr = ws_ptr<unsigned>(ws, lay.off_ch_ctr);
+        const unsigned nb = (unsigned)std::min<long long>(
+            std::min<long long>(n_chseg, kChainSlots), (long long)resident_workgroups());
         if (nb == 0) return;
+        // the segment counter starts from zero (a kernel, also inside a captured graph)
+        k_fill_u32<<<1, 64, 0, stream>>>(wa.chain_ctr, 0u, 1);
         const size_t lds = win_lds_bytes(wa.Sw, K, info.n_groups, 4);
         if (lay.psi64) {
             if (wa.small_wg) launch_chain<double, 256>(wa, nb, lds, stream);
@@ -2542,7 +2549,7 @@ int Solver::init(const Plan &p, char *workspace, size_t ws_bytes, hipStream_t st
     if (!rc) rc = reset();
     if (!rc && chain_only) {
         chain_only = false;
-        rc = set_chain(2);
+        rc = set_chain(1);
         chain_only = true;
         if (rc) set_error("a chain-only workspace needs the per-lane FP32 sweep (at most 8 groups)");
     }

@@ -50,7 +50,7 @@ class PlanInfo(C.Structure):
                 ("n_chunks", C.c_longlong), ("n_groups", C.c_int), ("tracks_per_wave", C.c_int),
                 ("dz", C.c_double), ("workspace_bytes", C.c_size_t), ("psi_bytes", C.c_size_t),
                 ("workspace_bytes_fp64", C.c_size_t), ("line_stride", C.c_int),
-                ("workspace_bytes_chain", C.c_size_t)]
+                ("workspace_bytes_chain", C.c_size_t), ("n_chain_segments", C.c_longlong)]
 
 
 class StoreInfo(C.Structure):
@@ -370,10 +370,8 @@ class Solver:
     def set_chain(self, on=True):
         """Chain-line sweeping (moc_solver_set_chain): every line swept whole
         from the z face it enters through to the one it leaves through, the
-        flux crossing reflective side faces within the sweep.  on: False/0,
-        True/1 (a workgroup per directed cycle and polar angle) or 2 (rising
-        and falling lines in workgroups of their own)."""
-        _check(lib().moc_solver_set_chain(self._h, int(on)))
+        flux crossing reflective side faces within the sweep."""
+        _check(lib().moc_solver_set_chain(self._h, 1 if on else 0))
 
     def set_window(self, threads=0):
         """Workgroup size of the per-lane sweep: 0 (automatic), 256, 512, 1024."""

@@ -276,12 +276,12 @@ def chain_study(name, iters=5, tol=1e-6, max_iters=2000, sizes=(0,)):
     s.set_source(prob.q)
     for nt in sizes:
         s.set_window(nt)
-        for chain in (0, 1, 2):
+        for chain in (0, 1):
             s.set_chain(chain)
             s.reset()
             s.iterate(1, stats=False)
             st = s.iterate(iters)
-            row = {"mode": ("lagged", "chain", "chain split")[chain], "threads": s.window()[0],
+            row = {"mode": ("lagged", "chain")[chain], "threads": s.window()[0],
                    "segments_per_window": s.window()[1], "sweep_ms_median": st["sweep_ms_median"],
                    "seg_group_per_s": st["seg_group_updates"] / (st["sweep_ms_median"] * 1e-3)}
             _log(f"chain {name}: {row}")
@@ -289,13 +289,13 @@ def chain_study(name, iters=5, tol=1e-6, max_iters=2000, sizes=(0,)):
     s.set_window(0)
     if tol > 0:
         out["converge"] = []
-        for chain in (0, 2):
+        for chain in (0, 1):
             s.set_chain(chain)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             phi, st = s.solve(tol=tol, max_iters=max_iters)
             torch.cuda.synchronize()
-            row = {"mode": "chain split" if chain else "lagged", "iters": st["iters"],
+            row = {"mode": "chain" if chain else "lagged", "iters": st["iters"],
                    "converged": st["converged"], "residual": st["residual"],
                    "wall_s": time.perf_counter() - t0, "sweep_ms_median": st["sweep_ms_median"]}
             _log(f"chain {name} converge: {row}")
@@ -332,7 +332,8 @@ def chain_only_study(name, iters=10):
            "sweep_ms_median": float(np.median(sweeps)),
            "seg_group_per_s": st["seg_group_updates"] / (float(np.median(sweeps)) * 1e-3),
            "residual_history": hist, "seg_group_updates_per_sweep": st["seg_group_updates"],
-           "link_errors": st["link_errors"], "window": s.window()}
+           "link_errors": st["link_errors"], "window": s.window(),
+           "segments": info["n_chain_segments"]}
     s.close()
     return out
 

@@ -159,18 +159,21 @@ def test_chain_window_sizes_agree(moc):
     assert ref is not None
 
 
-def test_chain_split_matches_oracle(moc, nthreads):
-    """Rising and falling lines in workgroups of their own (on = 2): the same
-    iterates as the oracle's chain mode."""
-    prob = P.small_lattice()
+def test_chain_segments_cover_every_line(moc, nthreads):
+    """A coarser problem whose cycles are cut into many segments (a line's
+    reach is short against the cycle): still every line swept once, as the
+    oracle's chain iterate."""
+    prob = P.small_lattice(n=4, height=2.0, n_layers=2, n_azim=16, n_polar=6, radial=0.1, axial=0.25)
     plan = moc.Plan(prob)
+    assert plan.info["n_chain_segments"] > 4 * 4
     s = moc.Solver(plan)
     s.set_source(prob.q)
-    s.set_chain(2)
+    s.set_chain(True)
     st = s.iterate(3)
     om = O.Model(prob, n_threads=nthreads)
     ophi, ores = om.solve(tol=0.0, max_iters=3, chain=True)
     assert _relerr(s.flux(), ophi) < TOL32
+    assert abs(st["leakage"] - ores["leakage"]) < TOL32 * ores["leakage"]
     assert st["seg_group_updates"] == 2 * om.info["n_segments"] * prob.n_groups
     assert st["link_errors"] == 0
 
