@@ -296,14 +296,14 @@ MOC_API int moc_solver_set_bundles(moc_solver *s, int mode);
  * leaving a track through a side face entering the reflected track within
  * the same sweep, instead of one sweep later through the boundary buffers
  * (the default, on = 0).  The fixed point is the same; the iterates differ
- * (no lag).  One workgroup sweeps one directed 2D cycle for one polar angle
- * (on = 1) or for the rising or the falling lines of one polar angle (on = 2,
- * twice the workgroups), unit after unit, so the sweep has far less
- * parallelism than the lagged one.  Needs vacuum top
- * and bottom faces, an even polar count and the per-lane FP32 sweep (at
- * most 8 groups); EINVAL otherwise, and moc_solve / moc_iterate /
- * moc_solve_eigen return EINVAL in chain mode with options that select
- * another sweep (FP64 or the naive exponential).  Drops captured steps. */
+ * (no lag).  Each directed 2D cycle is cut into segments of lines by where
+ * they enter the box (moc_plan_info.n_chain_segments in all); workgroups
+ * take segments in turn and sweep their units in cycle order, passing the
+ * flux in per-workgroup carry buffers.  Needs vacuum top and bottom faces,
+ * an even polar count and the per-lane FP32 sweep (at most 8 groups);
+ * EINVAL otherwise, and moc_solve / moc_iterate / moc_solve_eigen return
+ * EINVAL in chain mode with options that select another sweep (FP64 or the
+ * naive exponential).  Drops captured steps. */
 MOC_API int moc_solver_set_chain(moc_solver *s, int on);
 
 /* Eigenvalue mode: power iteration on k-eff (the multiplication factor the

@@ -75,9 +75,9 @@ struct WinArgs {
 // length lc, the unit's unrolled start u, and the workgroup's carries.
 struct ChainItem {
     int seg, nseg;
-    int par;        // carry buffer of this item (the next item's is par ^ 1)
     int cap;        // lines per stack in a carry buffer
-    void *carry;    // this workgroup's carry buffers
+    void *cur;      // this item's carry buffer [P stacks][cap][G]
+    void *next;     // the next item's
     double u, lc;
 };
 

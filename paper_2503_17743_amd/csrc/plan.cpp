@@ -533,10 +533,12 @@ std::string Plan::build(const moc_geometry &g, const moc_tracking &t, const moc_
             for (int n = P / 2; n < P; ++n) reach_max = std::max(reach_max, H / cot[tv.az * P + n]);
         }
         if (covered != 2 * n2d) return "internal: traversals do not cover every unit";
-        // segments of about the same length: at least four reaches long (a
-        // segment's units past its end carry only its last lines), and small
-        // enough that a few thousand of them share out the sweep
-        const double lseg = std::max(4.0 * reach_max, total / 2048.0);
+        // segments of about the same length: about 1024 of them to share out
+        // the sweep, but from one to four reaches long (a segment's units
+        // past its end carry only its last lines, so short segments repeat
+        // work: lattice64 ran 4.16 / 4.26 / 4.49 s with segments of 4, 2, 1
+        // reaches, lattice8 7.0 / 3.6 / 2.1 ms with 56, 120, 248 segments)
+        const double lseg = std::max(reach_max, std::min(4.0 * reach_max, total / 1024.0));
         struct Seg {
             int k, nk;
             double lc;

@@ -948,9 +948,8 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
             // the line's flux between windows (and on entry): its boundary
             // slot, or in the chain sweep its entry of the item's carry
             // buffer (parity, stack, line)
-            const long long slot = ci ? ((long long)(ci->par * P + n) * ci->cap + i)
-                                      : 2 * (a.trk_off[s] + i) + dir;
-            B *const cbuf = ci ? (B *)ci->carry : (B *)psi_in;
+            const long long slot = ci ? ((long long)n * ci->cap + i) : 2 * (a.trk_off[s] + i) + dir;
+            B *const cbuf = ci ? (B *)ci->cur : (B *)psi_in;
             const size_t hook = (size_t)unit * kItemStride + (size_t)(i - fi0) * G + g0;
             R psi[kGL];
 #pragma unroll
@@ -1217,9 +1216,9 @@ __device__ __forceinline__ void sweep_unit(const WinArgs &wa, int code, int unit
                         long long slot2 = successor_line(a, b, t, n, dir, base, c, n2, i2);
                         // chain sweep: the continuation is swept by the next
                         // item, from the other carry buffer
-                        if (ci && slot2 >= 0) slot2 = (long long)((ci->par ^ 1) * P + n2) * ci->cap + i2;
+                        if (ci && slot2 >= 0) slot2 = (long long)n2 * ci->cap + i2;
                         if (slot2 >= 0) {
-                            B *po = (ci ? (B *)ci->carry : (B *)psi_out) + slot2 * G + g0;
+                            B *po = (ci ? (B *)ci->next : (B *)psi_out) + slot2 * G + g0;
 #pragma unroll
                             for (int j = 0; j < kGL; ++j)
                                 if (j < ng) po[j] = (B)psi[j];
@@ -1311,7 +1310,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     __shared__ int s_seg;
     ChainItem ci;
     ci.cap = wa.chain_cap;
-    ci.carry = (B *)wa.chain_carry + (size_t)blockIdx.x * 2 * wa.s.P * wa.chain_cap * wa.s.G;
+    const size_t cstride = (size_t)wa.s.P * wa.chain_cap * wa.s.G;
+    B *const carry = (B *)wa.chain_carry + (size_t)blockIdx.x * 2 * cstride;
     for (;;) {
         if (threadIdx.x == 0) s_seg = (int)atomicAdd(wa.chain_ctr, 1u);
         __syncthreads();
@@ -1325,7 +1325,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         for (int i = i0; i < i1; ++i) {
             const int code = wa.chain_code[i];
             ci.u = wa.chain_u[i];
-            ci.par = (i - i0) & 1;
+            const int par = (i - i0) & 1;
+            ci.cur = carry + par * cstride;
+            ci.next = carry + (par ^ 1) * cstride;
             if (code & 1) sweep_unit<float, B, 0, 0, true, true, GC, true, NT>(wa, code, blockIdx.x, smem, false, &ci);
             else sweep_unit<float, B, 0, 0, false, true, GC, true, NT>(wa, code, blockIdx.x, smem, false, &ci);
             // the fluxes handed to the next unit are read by any wave of this
