@@ -185,6 +185,14 @@ def config_lattice64() -> Problem:
                     max_iters=50)
 
 
+def config_lattice64_fine() -> Problem:
+    """lattice64 with half the axial ray spacing (0.05 cm): twice the 3D
+    tracks, whose two boundary angular-flux buffers (about 420 GB) exceed one
+    GPU's memory; a chain-line sweep needs none of them."""
+    return _lattice("lattice64_fine", 5, 64, 200.0, 200, 4, 7, 64, 8, 0.03, 0.05,
+                    max_iters=50)
+
+
 def small_lattice(seed=11, n=3, height=3.0, n_layers=3, n_groups=3, n_mat=3,
                   n_azim=8, n_polar=4, radial=0.2, axial=0.3,
                   bc=REFLECTIVE_SIDES_VACUUM_Z, n_sectors=4, radius=0.35,
@@ -296,6 +304,7 @@ CONFIGS = {
     "lattice8": config_lattice8,
     "lattice32": config_lattice32,
     "lattice64": config_lattice64,
+    "lattice64_fine": config_lattice64_fine,
 }
 
 
