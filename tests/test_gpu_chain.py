@@ -227,6 +227,29 @@ def test_chain_eigenvalue_matches_oracle(moc, nthreads):
     assert np.max(np.abs(a[m] - b[m]) / b[m]) < 1e-5
 
 
+@pytest.mark.parametrize("case", ["one_layer", "two_polar", "tall_narrow"])
+def test_chain_degenerate_cases(moc, nthreads, case):
+    """One axial layer; the minimal polar quadrature (one angle each way);
+    a tall narrow box whose lines wrap round their short cycles many times
+    before they reach the other z face (many passes past the cycle origin)."""
+    if case == "one_layer":
+        prob = P.small_lattice(seed=31, n_layers=1, height=1.0)
+    elif case == "two_polar":
+        prob = P.small_lattice(seed=32, n_polar=2)
+    else:
+        prob = P.small_lattice(seed=34, n=1, height=12.0, n_layers=6, n_azim=4, n_polar=4,
+                               radial=0.1, axial=0.3)
+    plan = moc.Plan(prob)
+    s = moc.Solver(plan, chain_only=True)
+    s.set_source(prob.q)
+    st = s.iterate(2)
+    om = O.Model(prob, n_threads=nthreads)
+    ophi, ores = om.solve(tol=0.0, max_iters=2, chain=True)
+    assert _relerr(s.flux(), ophi) < TOL32
+    assert st["seg_group_updates"] == 2 * om.info["n_segments"] * prob.n_groups
+    assert st["link_errors"] == 0
+
+
 def test_chain_rejections(moc):
     """Chain mode needs vacuum top and bottom faces, and in chain mode the
     FP64 sweep is refused rather than run lagged."""
