@@ -230,10 +230,18 @@ class Solver:
     the default stream)."""
 
     def __init__(self, plan: Plan, device="cuda", workspace=None, fp64_boundary=None, walk="auto",
-                 stream="own", chain_only=False):
+                 stream="own", chain_only="auto"):
+        """chain_only: True gives a solver without boundary buffers (chain-line
+        sweeps only); "auto" does so when the full workspace would not fit in
+        the device's free memory and the plan allows chain sweeps; False never."""
         import torch
         self.plan = plan
         self.info = plan.info
+        if chain_only == "auto":
+            chain_only = False
+            if workspace is None and plan.info["workspace_bytes_chain"]:
+                free, _ = torch.cuda.mem_get_info(torch.device(device))
+                chain_only = plan.info["workspace_bytes"] + (1 << 30) > free
         if chain_only:
             # no boundary buffers: the solver sweeps chain lines only
             if not plan.info["workspace_bytes_chain"]:

@@ -250,6 +250,26 @@ def test_chain_degenerate_cases(moc, nthreads, case):
     assert st["link_errors"] == 0
 
 
+def test_solver_picks_chain_only_when_the_workspace_does_not_fit(moc):
+    """lattice64 with half the axial spacing: the full workspace (about 428 GB)
+    exceeds the GPU, so Solver(plan) makes a chain-only solver (about 7 GB)
+    and sweeps it; chain_only=False refuses to allocate rather than fall back."""
+    import torch
+    prob = P.get("lattice64_fine")
+    plan = moc.Plan(prob)
+    free, _ = torch.cuda.mem_get_info()
+    assert plan.info["workspace_bytes"] > free
+    s = moc.Solver(plan)
+    assert s.workspace.numel() < 16 * (1 << 30)
+    with pytest.raises(moc.MocError):
+        s.set_chain(False)
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    with pytest.raises(torch.OutOfMemoryError):
+        moc.Solver(plan, chain_only=False)
+
+
 def test_chain_rejections(moc):
     """Chain mode needs vacuum top and bottom faces, and in chain mode the
     FP64 sweep is refused rather than run lagged."""
