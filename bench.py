@@ -238,7 +238,7 @@ def small_workload(name, steps, oracle_iters, cpu_leg):
     from paper_2503_17743_amd import moc, problems as P
     prob = P.get(name)
     plan = moc.Plan(prob)
-    solver = moc.Solver(plan, fp64_boundary=False)
+    solver = moc.Solver(plan, fp64_boundary=False, chain_only=False)
     solver.set_source(prob.q)
     parity, cpu = None, None
     if cpu_leg:
@@ -385,7 +385,7 @@ def main():
     plan = moc.Plan(prob)
     log(f"{prob.name}: planned in {time.perf_counter() - t0:.1f} s, workspace "
         f"{plan.info['workspace_bytes'] / 1e9:.1f} GB")
-    solver = moc.Solver(plan, fp64_boundary=False, walk=args.walk)
+    solver = moc.Solver(plan, fp64_boundary=False, walk=args.walk, chain_only=False)
     solver.set_source(prob.q)
     log(f"{prob.name}: {args.warmup} warm-up + {args.steps} timed iterations ...")
     st, elapsed = timed_iterations(solver, args.steps, args.warmup, prob.name)
