@@ -7,9 +7,9 @@
   python -m paper_2503_17743_amd.study scale [--workload lattice64] [--iters 50]
       FP32 source iterations of the whole problem: time per sweep, residual
       history and the neutron balance of the last iteration.
-  python -m paper_2503_17743_amd.study eigen [--workload lattice8] [--iters 2000]
+  python -m paper_2503_17743_amd.study eigen [--workload lattice8] [--iters 2000] [--chain]
       Power iteration on k-eff (synthetic fission data, fissile inclusions)
-      to 1e-6: k, iterations and time per iteration.
+      to 1e-6: k, iterations and time per iteration (--chain: chain-line sweeps).
   python -m paper_2503_17743_amd.study exp [--workload lattice8] [--iters 10]
       Stored-segment sweep and work-unit schedules: median sweep time of the
       on-the-fly sweep under each schedule and of the stored-segment sweep.
@@ -132,14 +132,15 @@ def scale(name, iters, walk="auto"):
     return out
 
 
-def eigen(name, tol=1e-6, max_iters=2000, walk="auto"):
+def eigen(name, tol=1e-6, max_iters=2000, walk="auto", chain=False):
     """Power iteration on k-eff of a lattice with synthetic fission data
-    (fissile inclusion material): k, iterations, time per iteration."""
+    (fissile inclusion material): k, iterations, time per iteration; with
+    chain=True in a chain-only solver (chain-line sweeps)."""
     import torch
     prob = P.get(name)
     nsf, chi = P.fission_data(prob)
     plan = moc.Plan(prob)
-    s = moc.Solver(plan, fp64_boundary=False, walk=walk)
+    s = moc.Solver(plan, fp64_boundary=False, walk=walk, chain_only=bool(chain))
     _log(f"eigen {name}: power iteration to {tol:g} ...")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -151,7 +152,7 @@ def eigen(name, tol=1e-6, max_iters=2000, walk="auto"):
            "converged": st["converged"], "residual": st["residual"], "wall_s": wall,
            "ms_per_iteration": wall / st["iters"] * 1e3, "sweep_ms_median": st["sweep_ms_median"],
            "seg_group_updates_per_sweep": segg,
-           "seg_group_per_s_wall": segg * st["iters"] / wall, "walk": s.walk()}
+           "seg_group_per_s_wall": segg * st["iters"] / wall, "walk": s.walk(), "chain": bool(chain)}
     s.close()
     return out
 
@@ -347,6 +348,7 @@ def main(argv=None):
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--walk", choices=("auto", "lockstep", "lane"), default="auto")
     ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--chain", action="store_true", help="eigen: chain-line sweeps (chain-only solver)")
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
     if args.study == "precision":
@@ -362,7 +364,7 @@ def main(argv=None):
     elif args.study == "chain":
         out = chain_study(args.workload or "lattice8", args.iters or 5, tol=args.tol)
     elif args.study == "eigen":
-        out = eigen(args.workload or "lattice8", max_iters=args.iters or 2000)
+        out = eigen(args.workload or "lattice8", max_iters=args.iters or 2000, chain=args.chain)
     else:
         out = scale(args.workload or "lattice64", args.iters or 50, args.walk)
     print(json.dumps(out), flush=True)
