@@ -117,6 +117,7 @@ typedef struct {
                                   /* buffers (moc_solver_set_chain; 0: the plan has */
                                   /* no vacuum top and bottom faces)                */
     long long n_chain_segments;   /* independent jobs of a chain-line sweep        */
+    long long n_chain_items;      /* units they sweep, in all (moc_plan_chain)     */
 } moc_plan_info;
 
 /* Solve controls.  sweep_fp64 = 1 runs segment arithmetic and angular flux in
@@ -185,6 +186,13 @@ MOC_API int moc_plan_tracks2d(const moc_plan *plan, double *xy, double *length, 
                               long long *link, double *chain, int *sigma);
 MOC_API int moc_plan_stacks(const moc_plan *plan, double *zeta, long long *i_lo, long long *count);
 MOC_API int moc_plan_segments2d(const moc_plan *plan, double *pos, int *region, long long *first);
+/* Chain-line sweep segments (moc_solver_set_chain): first [n_chain_segments+1]
+ * item offsets; per segment k [n] (its index in its directed cycle), nk [n]
+ * (segments of that cycle) and lc [n] (the cycle's length); per item
+ * code [n_chain_items] (unit 2*t + dir) and u [n_chain_items] (the unit's
+ * start unrolled along the cycle).  Any pointer may be NULL. */
+MOC_API int moc_plan_chain(const moc_plan *plan, long long *first, int *k, int *nk, double *lc,
+                           int *code, double *u);
 /* Chunks: work item w = 2*chunk + dir covers stored tracks
  * [first_track, first_track + n_tracks) swept in direction dir. */
 MOC_API int moc_plan_chunk(const moc_plan *plan, long long chunk, long long *first_track,

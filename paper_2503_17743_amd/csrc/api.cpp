@@ -108,6 +108,24 @@ int moc_plan_stacks(const moc_plan *plan, double *zeta, long long *i_lo, long lo
     return MOC_OK;
 }
 
+int moc_plan_chain(const moc_plan *plan, long long *first, int *k, int *nk, double *lc, int *code,
+                   double *u) {
+    if (!plan) return fail(MOC_EINVAL, "NULL plan");
+    const moc::Plan &p = plan->p;
+    for (int64_t s = 0; s < p.n_chseg; ++s) {
+        if (k) k[s] = p.ch_k[s];
+        if (nk) nk[s] = p.ch_nk[s];
+        if (lc) lc[s] = p.ch_lc[s];
+    }
+    for (int64_t s = 0; s <= p.n_chseg; ++s)
+        if (first) first[s] = p.ch_first[s];
+    for (size_t i = 0; i < p.ch_code.size(); ++i) {
+        if (code) code[i] = p.ch_code[i];
+        if (u) u[i] = p.ch_u[i];
+    }
+    return MOC_OK;
+}
+
 int moc_plan_segments2d(const moc_plan *plan, double *pos, int *region, long long *first) {
     if (!plan) return fail(MOC_EINVAL, "NULL plan");
     const moc::Plan &p = plan->p;

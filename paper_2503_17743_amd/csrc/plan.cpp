@@ -618,6 +618,7 @@ moc_plan_info Plan::info() const {
     o.workspace_bytes_fp64 = make_layout(*this, true).total;
     o.workspace_bytes_chain = n_chseg > 0 ? l.off_psi0 : 0;
     o.n_chain_segments = n_chseg;
+    o.n_chain_items = (long long)ch_code.size();
     return o;
 }
 

@@ -50,7 +50,8 @@ class PlanInfo(C.Structure):
                 ("n_chunks", C.c_longlong), ("n_groups", C.c_int), ("tracks_per_wave", C.c_int),
                 ("dz", C.c_double), ("workspace_bytes", C.c_size_t), ("psi_bytes", C.c_size_t),
                 ("workspace_bytes_fp64", C.c_size_t), ("line_stride", C.c_int),
-                ("workspace_bytes_chain", C.c_size_t), ("n_chain_segments", C.c_longlong)]
+                ("workspace_bytes_chain", C.c_size_t), ("n_chain_segments", C.c_longlong),
+                ("n_chain_items", C.c_longlong)]
 
 
 class StoreInfo(C.Structure):
@@ -100,6 +101,7 @@ def lib():
         "moc_plan_tracks2d": ([VP] + [VP] * 6, C.c_int),
         "moc_plan_stacks": ([VP] + [VP] * 3, C.c_int),
         "moc_plan_segments2d": ([VP] + [VP] * 3, C.c_int),
+        "moc_plan_chain": ([VP] + [VP] * 6, C.c_int),
         "moc_plan_chunk": ([VP, C.c_longlong, C.POINTER(C.c_longlong), C.POINTER(C.c_int)], C.c_int),
         "moc_solver_create": ([VP, VP, C.c_size_t, VP, C.POINTER(VP)], C.c_int),
         "moc_solver_destroy": ([VP], None),
@@ -214,6 +216,14 @@ class Plan:
         first = np.zeros(self.info["n_2d_tracks"] + 1, np.int64)
         _check(lib().moc_plan_segments2d(self._h, _p(pos), _p(reg), _p(first)))
         return pos, reg, first
+
+    def chain(self):
+        """Segments of the chain-line sweep (moc_plan_chain)."""
+        ns, ni = self.info["n_chain_segments"], self.info["n_chain_items"]
+        out = dict(first=np.zeros(ns + 1, np.int64), k=np.zeros(ns, np.int32), nk=np.zeros(ns, np.int32),
+                   lc=np.zeros(ns), code=np.zeros(ni, np.int32), u=np.zeros(ni))
+        _check(lib().moc_plan_chain(self._h, *[_p(out[x]) for x in ("first", "k", "nk", "lc", "code", "u")]))
+        return out
 
     def chunk(self, c: int):
         ft, nt = C.c_longlong(), C.c_int()
