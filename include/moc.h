@@ -208,8 +208,8 @@ MOC_API int moc_plan_chunk(const moc_plan *plan, long long chunk, long long *fir
  * ws_bytes >= workspace_bytes in FP32.  A workspace of at least
  * workspace_bytes_chain (when that is nonzero) but less than workspace_bytes
  * makes a chain-only solver: it holds no boundary buffers, sweeps in chain
- * mode 2 (moc_solver_set_chain) and refuses to leave chain mode, as well as
- * moc_sweep_items and moc_gather_boundary.  ENOMEM below that.  The plan may
+ * mode (moc_solver_set_chain) and refuses to leave it, as well as
+ * moc_sweep_items and moc_get_boundary_flux.  ENOMEM below that.  The plan may
  * be destroyed afterwards. */
 MOC_API int moc_solver_create(const moc_plan *plan, void *dev_workspace, size_t ws_bytes,
                               void *stream, moc_solver **out);
