@@ -299,6 +299,29 @@ def chain_leg(name, iters, cpu_leg):
     }
 
 
+def chain_headline(prob, plan, steps, segg_lagged):
+    """Chain-line sweeps of the headline workload in a chain-only solver (no
+    boundary buffers): median sweep time, the same segment-group count as
+    the lagged sweep, and the two workspace sizes."""
+    from paper_2503_17743_amd import moc
+    solver = moc.Solver(plan, chain_only=True)
+    solver.set_source(prob.q)
+    log(f"{prob.name}: 1 + {steps} chain-line iterations (chain-only solver) ...")
+    solver.iterate(1, stats=False)
+    st = solver.iterate(steps)
+    solver.close()
+    return {
+        "iterations": steps,
+        "sweep_ms_median": st["sweep_ms_median"],
+        "seg_group_per_s": st["seg_group_updates"] / (st["sweep_ms_median"] * 1e-3),
+        "seg_group_updates_equal_lagged": st["seg_group_updates"] == segg_lagged,
+        "link_errors": st["link_errors"],
+        "workspace_bytes_chain_only": plan.info["workspace_bytes_chain"],
+        "workspace_bytes_lagged": plan.info["workspace_bytes"],
+        "segments": plan.info["n_chain_segments"],
+    }
+
+
 def roofline(segg, sweep_s, counters):
     """The sweep's binding roof: vector ALU issue (measured wave64 VALU issue
     slots per launch, SQ_ACTIVE_INST_VALU, in which a transcendental counts
@@ -340,6 +363,8 @@ def main():
     ap.add_argument("--chain-workload", default="lattice8",
                     help="a small problem also swept in chain-line mode ('' to skip)")
     ap.add_argument("--chain-iters", type=int, default=5)
+    ap.add_argument("--chain-steps", type=int, default=2,
+                    help="chain-line sweeps of the headline workload in a chain-only solver (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=32,
                     help="requests in the serving comparison (0: skip it)")
@@ -403,6 +428,11 @@ def main():
         log(f"{prob.name}: parity {parity}")
     solver_walk = solver.walk()
     solver.close()
+    torch.cuda.empty_cache()
+    chain_head = None
+    if args.chain_steps > 0 and plan.info["workspace_bytes_chain"]:
+        chain_head = chain_headline(prob, plan, args.chain_steps, segg)
+        log(f"{prob.name}: chain-line sweep {chain_head['sweep_ms_median']:.1f} ms")
 
     line = {
         "metric": "segment-group integrations/s at 1e-5 vs FP64",
@@ -432,6 +462,7 @@ def main():
             "sampled_oracle_parity": parity,
             "small_workload": small,
             "chain_line": chain,
+            "chain_line_headline": chain_head,
         },
         "roofline": roofline(segg, sweep_s, load_counters(prob.name)),
         "cpu_baseline": cpu,
